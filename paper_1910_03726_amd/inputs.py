@@ -1,0 +1,77 @@
+"""Seeded synthetic inputs for MGRIT/Parareal on periodic linear advection.
+
+This module holds no arithmetic of the method: it only draws the seeded
+initial conditions and initial iterates that both the HIP path and the
+CPU oracle are given, and names the workloads by their sizes.
+
+Inputs (the paper's workload is itself synthetic, Sec. 2.1):
+* grid x_i = -1 + i dx, dx = 2/n_x, periodic (Sec. 2.1);
+* u0 = sum_{k=1}^{K} k^{-decay} (a_k cos(pi k x) + b_k sin(pi k x)),
+  a_k, b_k ~ N(0, 1) from numpy's PCG64 ``default_rng(seed)``; the paper's
+  own u0 = sin^4(pi x) is available as ``sin4``;
+* initial iterate: uniform U[0, 1) at every C-point except t = 0
+  (Sec. 2.2 set-up), from ``default_rng(seed)``.
+"""
+
+import numpy as np
+
+
+def grid(nx):
+    return -1.0 + (2.0 / nx) * np.arange(nx)
+
+
+def fourier_u0(nx, nmodes, seed, decay=0.0):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(nmodes)
+    b = rng.standard_normal(nmodes)
+    x = grid(nx)
+    u = np.zeros(nx)
+    for k in range(1, nmodes + 1):
+        amp = float(k) ** (-decay)
+        u += amp * (a[k - 1] * np.cos(np.pi * k * x)
+                    + b[k - 1] * np.sin(np.pi * k * x))
+    return u
+
+
+def sin4(nx):
+    return np.sin(np.pi * grid(nx)) ** 4
+
+
+def random_iterate(npoints, nx, seed):
+    """U[0,1) values for ``npoints`` time levels (row 0 is replaced by u0)."""
+    return np.random.default_rng(seed).random((npoints, nx))
+
+
+# Courant numbers c = alpha dt/dx of the workloads.  ERK: 85% of the Table 1
+# CFL limit (1, 1/2, 1.62589, 1.04449, 1.96583); SDIRK: c = 4 (Sec. 2.1).
+CFL_LIMIT_TABLE1 = {1: 1.0, 2: 0.5, 3: 1.62589, 4: 1.04449, 5: 1.96583}
+
+
+def erk_cfl(p, fraction=0.85):
+    return fraction * CFL_LIMIT_TABLE1[p]
+
+
+# The four single-solve workloads (sizes, scheme, solver shape, seeds).
+WORKLOADS = {
+    "erk1_u1_nx64_nt256_m4_2level": dict(
+        scheme="ERK1", nx=64, nt=256, cfl=erk_cfl(1), m=4, levels=2,
+        cycle="V", precision="fp64", psi_rule="window", psi_widths=[3],
+        u0=dict(nmodes=4, decay=0.0, seed=0), init_seed=1),
+    "erk3_u3_nx4096_nt16384_m8_fcycle": dict(
+        scheme="ERK3", nx=4096, nt=16384, cfl=erk_cfl(3), m=8, levels=4,
+        cycle="F", precision="fp64", psi_rule="window", psi_widths=None,
+        u0=dict(nmodes=8, decay=2.0, seed=0), init_seed=1),
+    "sdirk3_u3_nx2048_nt8192_m16_2level": dict(
+        scheme="SDIRK3", nx=2048, nt=8192, cfl=4.0, m=16, levels=2,
+        cycle="V", precision="fp64", psi_rule="eta", psi_widths=None,
+        u0=dict(nmodes=8, decay=0.0, seed=0), init_seed=1),
+    "erk5_u5_nx8192_nt65536_m8_fp32relax": dict(
+        scheme="ERK5", nx=8192, nt=65536, cfl=erk_cfl(5), m=8, levels=5,
+        cycle="V", precision="fp32", psi_rule="window", psi_widths=None,
+        u0=dict(nmodes=16, decay=0.0, seed=0), init_seed=1),
+}
+
+
+def workload_u0(w):
+    return fourier_u0(w["nx"], w["u0"]["nmodes"], w["u0"]["seed"],
+                      w["u0"]["decay"])

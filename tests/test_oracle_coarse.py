@@ -1,0 +1,157 @@
+"""Pins for the oracle's coarse operators (Sec. 3-4: eqs. (7)-(10)).
+
+Remark 1 (unit weight = truncation), Lemma 2 (real solution), the exact
+fit of a full pattern, the circulant eigenvalue identity, Table 4's
+operator complexities and a brute-force check of the two-level bound
+eq. (7) against the oracle's own FCF iteration.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import coarse, mgrit, rk
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "paper_tables.json")))
+
+
+def _disc(scheme, nx):
+    return rk.Discretization(scheme, nx, rk.paper_cfl(scheme))
+
+
+def test_taps_eigenvalues_are_dft_of_first_column():
+    nx = 40
+    rng = np.random.default_rng(0)
+    offs = np.array([0, 3, 7, 39])
+    w = rng.standard_normal(4)
+    col = np.zeros(nx)
+    col[offs] = w
+    assert np.allclose(coarse.taps_eigenvalues(offs, w, nx), np.fft.fft(col))
+    # and they are the eigenvalues of the stencil's action
+    k = 5
+    mode = np.exp(2j * np.pi * k * np.arange(nx) / nx)
+    out = coarse.apply_taps(offs, w, np.real(mode)) + \
+        1j * coarse.apply_taps(offs, w, np.imag(mode))
+    assert np.allclose(out, coarse.taps_eigenvalues(offs, w, nx)[k] * mode)
+
+
+@pytest.mark.parametrize("scheme", ["ERK3", "SDIRK3"])
+def test_phi_m_first_column_is_m_steps(scheme):
+    nx, m = 64, 4
+    d = _disc(scheme, nx)
+    col, im = coarse.phi_m_first_column(d.eigenvalues(), m)
+    e0 = np.zeros(nx)
+    e0[0] = 1.0
+    assert im < 1e-14
+    assert np.max(np.abs(col - d.propagate(e0, m))) < 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["ERK1", "ERK3", "SDIRK3"])
+def test_remark1_unit_weight_is_truncation(scheme):
+    # Remark 1: with W = I, eq. (9) is solved by psi = R phi~^m.
+    nx, m = 128, 8
+    d = _disc(scheme, nx)
+    lam = d.eigenvalues()
+    col, _ = coarse.phi_m_first_column(lam, m)
+    offs = coarse.best_window(col, 9)
+    psi, im = coarse.lsq_psi(lam, m, offs, w=np.ones(nx))
+    assert np.max(np.abs(psi - col[offs])) < 1e-13
+    assert im < 1e-12
+
+
+def test_full_pattern_recovers_phi_m():
+    # With every entry free, the minimizer is Psi = Phi^m (Sec. 4).
+    nx, m = 32, 4
+    d = _disc("ERK3", nx)
+    lam = d.eigenvalues()
+    col, _ = coarse.phi_m_first_column(lam, m)
+    psi, _ = coarse.lsq_psi(lam, m, np.arange(nx))
+    assert np.max(np.abs(psi - col)) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,m", [("ERK1", 4), ("ERK3", 8), ("ERK5", 16),
+                                      ("SDIRK3", 16), ("SDIRK4", 64),
+                                      ("SDIRK1", 2)])
+def test_lemma2_solution_is_real(scheme, m):
+    # Lemma 2: the least-squares solution is real; numerically the
+    # imaginary part stays below the 1e-8 acceptance flag for the
+    # characteristic (Phi^m-based) patterns.
+    d = _disc(scheme, 256)
+    H = coarse.build_hierarchy(d, m, 2)
+    assert H[0]["max_imag"] < coarse.IMAG_FLAG
+    # the theta = 0 mode carries weight 1/eps^2, so mu_0 = sum psi ~ 1
+    assert abs(np.sum(H[0]["weights"]) - 1.0) < 1e-5
+
+
+def test_eta_pattern_config3_shape():
+    # SDIRK3+U3, c = 4, m = 16, eta = 0.02 (Sec. 4.6): the pattern sits
+    # around the characteristic departure point m c = 64 grid points upwind.
+    d = _disc("SDIRK3", 2048)
+    H = coarse.build_hierarchy(d, 16, 2)
+    offs = H[0]["offsets"]
+    assert 30 <= len(offs) <= 60
+    assert offs.min() > 0 and offs.max() < 128
+    assert abs(np.mean(offs) - 64) < 12
+
+
+def test_operator_complexity_table4():
+    # Eq. (10) with nnz(Phi) = 2 and nnz(Psi_l) = 3, 6, 11, 21 (m = 4)
+    # reproduces Table 4's ERK1+U1 complexities for 2..5 levels to the
+    # printed digits (12 non-zeros on level 4 would print 1.66, not 1.65).
+    want = GOLD["table4_multilevel_v_m4"]["ERK1_OC"]
+    nnz = [2, 3, 6, 11, 21]
+    for L in (2, 3, 4, 5):
+        oc = coarse.operator_complexity(nnz[:L], 4)
+        assert round(oc, 2) == want[L - 2], (L, oc)
+    assert round(coarse.operator_complexity([2, 3, 6, 12], 4), 2) == 1.66
+    # reference case nnz(Psi) = nnz(Phi): bounded by 1 + 1/(m-1)
+    assert coarse.operator_complexity([5] * 12, 4) < 1 + 1 / 3
+    assert abs(coarse.operator_complexity([5, 5], 4) - (1 + 1 / 4)) < 1e-15
+
+
+def test_cyclic_span_and_window():
+    n = 20
+    assert coarse.cyclic_span([18, 19, 0, 1], n) == 4
+    assert coarse.cyclic_span([3, 7], n) == 5
+    col = np.zeros(n)
+    col[[18, 19, 0]] = [1.0, 2.0, 1.0]
+    assert sorted(coarse.best_window(col, 3).tolist()) == [0, 18, 19]
+
+
+@pytest.mark.parametrize("lam,dmu,m", [
+    (0.95 * np.exp(0.3j), 0.05 * np.exp(0.7j), 4),
+    (0.8, 0.1, 4),
+    (0.97 * np.exp(0.2j), 0.03 * np.exp(-1.0j), 8),
+])
+def test_two_level_bound_eq7_brute_force(lam, dmu, m):
+    """Eq. (7) against the oracle's own two-level FCF iteration.
+
+    For one Fourier mode, Phi and Psi are the scalars lambda and mu.  The
+    C-point error propagator of one FCF iteration, built column by column
+    from the oracle, has 2-norm <= the bound / sqrt(m) (the sqrt(m) is the
+    factor of the full-grid norm), and it approaches that value as n_t
+    grows (sharp up to O(m/n_t)).
+    """
+    mu = lam ** m * (1 + dmu)
+    op = lambda X: lam * X
+    cop = lambda X: mu * X
+    nc = 256
+    E = np.zeros((nc, nc), complex)
+    for i in range(nc):
+        u = np.zeros((nc + 1, 1), complex)
+        u[i + 1, 0] = 1.0
+        v = mgrit.fc_relax(op, u, None, m)
+        r = mgrit.c_residual(op, v, None, m)
+        E[:, i] = (v + mgrit.sequential_solve(cop, r))[1:, 0]
+    nrm = np.linalg.norm(E, 2)
+    b = coarse.two_level_bound(lam, mu, m, nc * m) / np.sqrt(m)
+    assert nrm <= b * (1 + 1e-10)
+    assert nrm >= 0.95 * b
+
+
+def test_bound_vanishes_for_ideal_psi():
+    lam = 0.9 * np.exp(0.4j)
+    assert coarse.two_level_bound(lam, lam ** 4, 4, 64) == 0.0
