@@ -37,10 +37,11 @@ def eta_tol(p, m):
 # ---------------------------------------------------------------------------
 def taps_eigenvalues(offsets, weights, nx):
     """mu_k = sum_t w_t exp(-2 pi i k o_t / n_x), k = 0..n_x-1."""
-    k = np.arange(nx)
+    k = np.arange(nx, dtype=np.int64)
     mu = np.zeros(nx, dtype=complex)
     for o, w in zip(offsets, weights):
-        mu += w * np.exp(-2j * np.pi * k * (o % nx) / nx)
+        # reduce k*o mod n in integers so the angle stays in [0, 2 pi)
+        mu += w * np.exp(-2j * np.pi * ((k * (int(o) % nx)) % nx) / nx)
     return mu
 
 
@@ -85,9 +86,10 @@ def lsq_psi(eigs, m, offsets, w=None):
     n = eigs.size
     w = weights(eigs) if w is None else np.asarray(w, dtype=float)
     sw = np.sqrt(w)
-    k = np.arange(n)
-    offs = np.asarray(offsets) % n
-    M = sw[:, None] * np.exp(-2j * np.pi * np.outer(k, offs) / n)
+    k = np.arange(n, dtype=np.int64)
+    offs = np.asarray(offsets, dtype=np.int64) % n
+    # exp(-2 pi i k o / n) with k*o reduced mod n in integers
+    M = sw[:, None] * np.exp(-2j * np.pi * (np.outer(k, offs) % n) / n)
     rhs = sw * eigs ** m
     sol, *_ = np.linalg.lstsq(M, rhs, rcond=None)
     return np.real(sol), float(np.max(np.abs(np.imag(sol))))
@@ -113,7 +115,8 @@ def cyclic_span(offsets, n):
 
 def best_window(col, width):
     """Contiguous cyclic window [a, a+width) maximizing sum |phi~^m| inside;
-    the smallest such a on ties.  Returns the offsets a..a+width-1 (mod n).
+    the smallest such a on ties (sums within a relative 1e-12 of the
+    maximum count as ties).  Returns the offsets a..a+width-1 (mod n).
 
     This is the deterministic stand-in for the paper's hand-chosen
     contiguous Phi^m-based patterns of Sec. 4.3 (the chosen patterns are
@@ -125,7 +128,7 @@ def best_window(col, width):
     ext = np.concatenate([a, a[:width]])
     csum = np.concatenate([[0.0], np.cumsum(ext)])
     sums = csum[width:width + n] - csum[:n]
-    start = int(np.argmax(sums))
+    start = int(np.nonzero(sums >= sums.max() * (1.0 - 1e-12))[0][0])
     return (start + np.arange(width)) % n
 
 
@@ -145,7 +148,12 @@ def signed_offsets(offsets, n):
 # Coarse operators for a level hierarchy (Sec. 4.4)
 # ---------------------------------------------------------------------------
 def fine_nnz(disc):
-    """nnz of the (ERK) fine operator: taps of R(dt L) as a polynomial."""
+    """nnz of the (ERK) fine operator: taps of R(dt L) as a polynomial.
+
+    SDIRK steppers are dense (Corollary 1); the window rule then uses only
+    the threshold span, so 0 is returned for them."""
+    if disc.scheme.startswith("SDIRK"):
+        return 0
     col, _ = first_column_from_eigs(disc.eigenvalues())
     return int(np.count_nonzero(np.abs(col) > 1e-13 * np.abs(col).max()))
 

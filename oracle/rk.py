@@ -211,6 +211,24 @@ class Discretization:
         # l(theta) uses this object's dx; only n_x = self.nx is meaningful.
         return self.stability_function(dt * self.symbol_L(theta))
 
+    def spectral_propagate(self, u0, nsteps):
+        """Phi^n u0 in closed form: Phi is circulant with eigenvalues lambda_k
+        on the DFT modes (Lemma 1), so Phi^n u0 = F^{-1} diag(lambda^n) F u0.
+
+        lambda^n is formed by repeated squaring; its relative rounding grows
+        like n * eps, so this is for long horizons where stepping is slow.
+        """
+        lam = self.eigenvalues()
+        p = np.ones_like(lam)
+        base = lam.copy()
+        n = int(nsteps)
+        while n:
+            if n & 1:
+                p = p * base
+            base = base * base
+            n >>= 1
+        return np.real(np.fft.ifft(p * np.fft.fft(u0, axis=-1), axis=-1))
+
     def dense_phi(self):
         """Phi as a dense n_x x n_x matrix, built from the block form of the
         Runge-Kutta step rather than by stepping:
