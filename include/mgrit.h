@@ -1,0 +1,222 @@
+/*
+ * mgrit.h -- C-ABI of libmgrit: MGRIT / Parareal for the periodic
+ * constant-coefficient linear advection equation u_t + alpha u_x = 0 on
+ * x in [-1, 1), on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: De Sterck, Falgout, Friedhoff, Krzysik, MacLachlan, "Optimizing
+ * MGRIT and Parareal coarse-grid operators for linear advection"
+ * (Numer. Linear Algebra Appl. 2021, arXiv:1910.03726).
+ *
+ * Space-time problem (Sec. 2.1-2.2, eq. (3)): n_x periodic unknowns,
+ * dx = 2/n_x, x_i = -1 + i dx; Courant number c = alpha dt/dx (eq. (5));
+ * n_t steps u^{n+1} = Phi u^n from u^0 = u0, with Phi one step of a
+ * Runge-Kutta method (ERKp or SDIRKp, Appendix A) applied to the p-th order
+ * upwind discretization Up of -alpha d/dx (Sec. 2.1).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success, a negative MGRIT_E* code otherwise; no C++
+ *     exception crosses this boundary.  mgrit_strerror() names the code.
+ *   - Pointers named *_dev are device pointers (HIP, the current device of
+ *     the plan); *_host are host pointers.  The caller owns every buffer it
+ *     passes; a plan owns its own device workspace and copies of all taps.
+ *   - Space-time arrays are row-major [time level][n_x], FP64.
+ *   - A periodic stencil (mgrit_taps) means
+ *         (Psi u)_i = sum_t weight[t] * u[(i - offset[t]) mod n_x],
+ *     i.e. the circulant matrix whose first column holds weight[t] at row
+ *     offset[t] (Sec. 4.1).  Offsets may be any integers.
+ *   - Entry points that launch GPU work run on the plan's HIP stream.
+ *     mgrit_solve and mgrit_plan_create return only after their GPU work
+ *     has finished; phi_apply_batch is asynchronous on the stream.
+ *   - A plan is not thread-safe: calls on one plan must not overlap.
+ */
+#ifndef MGRIT_H
+#define MGRIT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define MGRIT_OK 0
+#define MGRIT_EINVAL (-1)     /* invalid argument or unsupported shape       */
+#define MGRIT_EUNSTABLE (-2)  /* ERK Courant number above the CFL limit       */
+#define MGRIT_ENOMEM (-3)     /* device or host allocation failed            */
+#define MGRIT_EHIP (-4)       /* a HIP runtime call failed                    */
+#define MGRIT_ENOTCONV (-5)   /* maxit reached above tol (history is filled)  */
+#define MGRIT_EDIVERGED (-6)  /* non-finite residual norm                     */
+#define MGRIT_EIMAG (-7)      /* least-squares imaginary part above 1e-8      */
+#define MGRIT_ENODEV (-8)     /* no usable gfx950 device                      */
+#define MGRIT_ECAPACITY (-9)  /* caller's output arrays are too small         */
+#define MGRIT_EBUSY (-10)     /* serving: admission refused (HBM budget)      */
+
+/* ---- discretizations (Sec. 2.1; tableaux of Appendix A) ----------------- */
+#define MGRIT_ERK1 1
+#define MGRIT_ERK2 2
+#define MGRIT_ERK3 3
+#define MGRIT_ERK4 4
+#define MGRIT_ERK5 5
+#define MGRIT_SDIRK1 11
+#define MGRIT_SDIRK2 12
+#define MGRIT_SDIRK3 13
+#define MGRIT_SDIRK4 14
+
+/* ---- solver options ----------------------------------------------------- */
+#define MGRIT_CYCLE_V 0      /* V-cycles (Sec. 4.4)                           */
+#define MGRIT_CYCLE_F 1      /* F-cycles: coarse problem by F- then V-cycle   */
+#define MGRIT_RELAX_FCF 0    /* FCF-relaxation (Sec. 2.2, the paper's choice) */
+#define MGRIT_RELAX_F 1      /* F-relaxation (Parareal)                       */
+#define MGRIT_FP64 0         /* all arithmetic in FP64                        */
+#define MGRIT_FP32_RELAX 1   /* FP32 relaxation inside FP64 iterative refinement */
+
+/* coarse-operator pattern rules for mgrit_psi_optimize */
+#define MGRIT_PSI_AUTO 0     /* ETA for SDIRK, WINDOW for ERK                 */
+#define MGRIT_PSI_WINDOW 1   /* contiguous window of Phi^m (Sec. 4.3)         */
+#define MGRIT_PSI_ETA 2      /* thresholding |phi^m| >= eta max (Sec. 4.6)    */
+#define MGRIT_PSI_REDISC 3   /* rediscretization: ERK Phi with step m^(l-1) dt */
+
+/* what mgrit_solve writes to u_out_dev */
+#define MGRIT_OUT_NONE 0     /* nothing                                       */
+#define MGRIT_OUT_FINAL 1    /* u^{n_t}: n_x values                           */
+#define MGRIT_OUT_CPOINTS 2  /* u^{jm}, j = 0..n_t/m: (n_t/m + 1) x n_x       */
+#define MGRIT_OUT_ALL 3      /* u^n, n = 0..n_t: (n_t + 1) x n_x              */
+
+typedef struct {
+    int nnz;        /* number of taps (in: capacity for outputs)             */
+    int* offset;    /* nnz offsets (caller-owned)                            */
+    double* weight; /* nnz weights (caller-owned)                            */
+} mgrit_taps;
+
+typedef struct mgrit_plan_s* mgrit_plan_t;
+
+/* Statistics of the last mgrit_solve on a plan. */
+typedef struct {
+    int iterations;        /* fine-level coarse-grid corrections applied      */
+    int outer_iterations;  /* FP64 refinement steps (MGRIT_FP32_RELAX), else 0 */
+    int fine_passes_fp64;  /* fine-level relaxation passes run in FP64        */
+    int fine_passes_fp32;  /* fine-level relaxation passes run in FP32        */
+    double final_residual; /* sqrt(dx dt sum r^2) of the returned iterate     */
+    double solve_ms;       /* wall time of the solve (host clock)             */
+} mgrit_stats;
+
+/* Per-kernel-class GPU time, collected with HIP events when profiling is on. */
+#define MGRIT_PROF_RELAX_FINE 0   /* fine-level relaxation passes (A and B) */
+#define MGRIT_PROF_RELAX_COARSE 1 /* relaxation on levels >= 2              */
+#define MGRIT_PROF_COARSEST 2     /* sequential coarsest-level sweeps       */
+#define MGRIT_PROF_NORM 3         /* residual-norm reductions               */
+#define MGRIT_PROF_OTHER 4        /* interpolation, axpy, copies            */
+#define MGRIT_PROF_CLASSES 5
+typedef struct {
+    double ms[MGRIT_PROF_CLASSES];    /* summed kernel time per class      */
+    long long launches[MGRIT_PROF_CLASSES];
+    double fine_dof_steps;            /* fine DOF-steps executed by class 0 */
+} mgrit_profile;
+
+/* ---- host-only setup (no GPU needed) ------------------------------------ */
+
+/* Library version, e.g. 100 for 1.0.0. */
+int mgrit_version(void);
+
+/* Static description of a return code; never NULL. */
+const char* mgrit_strerror(int code);
+
+/* max over theta in [0, pi] of |R(c * s(theta))|, the amplification of one
+ * step of `scheme` on Fourier mode theta (Lemma 1; used for the CFL limit of
+ * eq. (5) / Table 1).  Writes *amp.  Host only. */
+int mgrit_max_amplification(int scheme, double cfl, double* amp);
+
+/* Phi of an ERK scheme as one periodic stencil (Corollary 1: Phi = R(dt L)
+ * is a sparse circulant), offsets folded into [0, n_x).  Up to `capacity`
+ * taps are written to offsets/weights; *nnz receives the count.  SDIRK
+ * schemes return MGRIT_EINVAL (their Phi is dense).  Host only. */
+int mgrit_phi_taps(int scheme, double cfl, int nx, int capacity, int* offsets,
+                   double* weights, int* nnz);
+
+/* Coarse operators Psi_2..Psi_levels of an MGRIT hierarchy (Sec. 4, 4.4,
+ * 4.6): Phi_{l+1} minimizes the weighted spectral error of eq. (9) against
+ * Phi_l^m over the sparsity pattern given by `rule`:
+ *   MGRIT_PSI_WINDOW: contiguous window of phi~^m = first column of Phi_l^m;
+ *       width widths[l-1] if `widths` is non-NULL, else
+ *       max(nnz(Phi_l), span of {o : |phi~^m_o| >= 0.02 max}); placed to
+ *       maximize the sum of |phi~^m| inside (smallest start on ties);
+ *   MGRIT_PSI_ETA: {o : |phi~^m_o| >= eta max} with `eta`, or the table of
+ *       Sec. 4.6 for (p, m) if eta <= 0;
+ *   MGRIT_PSI_REDISC: ERK only; Psi_l = the ERK stencil at Courant number
+ *       m^(l-1) c (no least squares).
+ * Weights w_k = 1/(1 - |lambda_k| + 1e-6)^2 on the eigenvalues of Phi_l.
+ * out[l-2] for l = 2..levels must carry arrays with room for out[.].nnz
+ * taps (capacity on input, count on output).  *max_imag (may be NULL)
+ * receives the largest imaginary part over all levels; above 1e-8 the call
+ * returns MGRIT_EIMAG (outputs still written).  Host only. */
+int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels,
+                       int rule, const int* widths, double eta,
+                       mgrit_taps* out, double* max_imag);
+
+/* ---- plans and solves (GPU) --------------------------------------------- */
+
+/* Create a plan for n_x, n_t, alpha, Courant number c, scheme, coarsening
+ * factor m and `levels` >= 2 levels (n_t divisible by m^(levels-1); each
+ * level has >= 2 coarse intervals).  psi: levels-1 coarse stencils
+ * (Psi_2..Psi_levels), copied into the plan.  cycle/relax/precision: the
+ * MGRIT_* options above.  hip_stream: a hipStream_t (NULL = default
+ * stream).  ERK plans with c above the CFL limit (amplification > 1+1e-6)
+ * return MGRIT_EUNSTABLE.  SDIRK plans need n_x a multiple of 64.
+ * Allocates the device workspace; *plan receives the handle. */
+int mgrit_plan_create(mgrit_plan_t* plan, int nx, int nt, double alpha,
+                      double cfl, int scheme, int m, int levels,
+                      const mgrit_taps* psi, int cycle, int relax,
+                      int precision, void* hip_stream);
+
+/* Solve the space-time system to sqrt(dx dt sum r^2) <= tol (Sec. 2.2).
+ *   u0_dev:    n_x initial values u^0 (device).
+ *   uinit_dev: initial iterate at the C-points, (n_t/m + 1) x n_x (row 0 is
+ *              ignored and replaced by u0), or NULL for the plan's seeded
+ *              U[0,1) iterate (splitmix64 stream of mgrit_plan_set_seed).
+ *   maxit:     maximum coarse-grid corrections (>= 0).
+ *   u_out_dev: output per out_kind (MGRIT_OUT_*), may be NULL for NONE.
+ *   res_hist_host: may be NULL, else room for maxit+1 doubles: the
+ *              residual norm before each correction (FP64 refinement
+ *              residuals for MGRIT_FP32_RELAX).
+ *   iters_out: may be NULL; receives the number of corrections.
+ * Returns MGRIT_ENOTCONV if maxit is reached (outputs still written),
+ * MGRIT_EDIVERGED on a non-finite norm.  Synchronous. */
+int mgrit_solve(mgrit_plan_t plan, const double* u0_dev,
+                const double* uinit_dev, double tol, int maxit,
+                double* u_out_dev, int out_kind, double* res_hist_host,
+                int* iters_out);
+
+/* out[b] = Phi^k in[b] for b = 0..batch-1, rows of n_x values (device,
+ * row-major, in and out may not overlap).  The fine stepper of the plan in
+ * the plan's precision of relaxation; asynchronous on the plan stream. */
+int phi_apply_batch(mgrit_plan_t plan, const double* in_dev, double* out_dev,
+                    int batch, int ksteps);
+
+/* Device bytes the plan holds (its HBM footprint, for admission). */
+int mgrit_plan_bytes(mgrit_plan_t plan, size_t* hbm_bytes);
+
+/* Seed of the U[0,1) initial iterate used when uinit_dev is NULL. */
+int mgrit_plan_set_seed(mgrit_plan_t plan, unsigned long long seed);
+
+/* Statistics of the last solve. */
+int mgrit_get_stats(mgrit_plan_t plan, mgrit_stats* stats);
+
+/* Turn per-kernel HIP-event timing on (1) or off (0); turning it on clears
+ * the counters.  mgrit_get_profile reads them. */
+int mgrit_set_profiling(mgrit_plan_t plan, int enable);
+int mgrit_get_profile(mgrit_plan_t plan, mgrit_profile* prof);
+
+/* Operator complexity of the plan's hierarchy, eq. (10). */
+int mgrit_operator_complexity(mgrit_plan_t plan, double* oc);
+
+/* Short text naming the kernels the plan selected (static per plan). */
+const char* mgrit_plan_describe(mgrit_plan_t plan);
+
+/* Release the plan and its device memory (NULL is a no-op). */
+void mgrit_destroy(mgrit_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGRIT_H */

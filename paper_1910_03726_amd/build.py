@@ -1,0 +1,79 @@
+"""Build libmgrit.so (HIP for gfx950) in-tree.
+
+    python -m paper_1910_03726_amd.build [-j N]
+
+Compiles every source under csrc/ (the k_stencil shards once per precision
+and chunk length) into _build/ and links paper_1910_03726_amd/libmgrit.so.
+Always rebuilds.
+"""
+
+import argparse
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libmgrit.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+# Packed FP32 instructions are disabled for every device pass.
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument"]
+CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+STENCIL_K = (1, 2, 4, 8, 16, 32)
+
+
+def _jobs():
+    objs = []
+    objs.append(("g++", os.path.join(CSRC, "setup.cpp"), "setup.o", []))
+    objs.append((HIPCC, os.path.join(CSRC, "plan.cpp"), "plan.o", ["-x", "hip"]))
+    objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
+    for prec in (0, 1):
+        objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),
+                     f"inst_sdirk_{prec}.o", [f"-DMGR_PREC={prec}"]))
+        for k in STENCIL_K:
+            objs.append((HIPCC, os.path.join(CSRC, "inst_stencil.hip"),
+                         f"inst_stencil_{prec}_{k}.o",
+                         [f"-DMGR_PREC={prec}", f"-DMGR_K={k}"]))
+    return objs
+
+
+def _compile(job):
+    cc, src, obj, extra = job
+    out = os.path.join(BUILD, obj)
+    flags = HIP_FLAGS if cc == HIPCC else CXX_FLAGS
+    cmd = [cc] + flags + extra + ["-I", CSRC, "-c", src, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return out
+
+
+def build(jobs=None, verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    work = _jobs()
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, work))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB} from {len(objs)} objects")
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("-j", type=int, default=None)
+    a = ap.parse_args()
+    build(a.j, verbose=True)
+    sys.exit(0)

@@ -1,0 +1,83 @@
+// Structures shared by the host planner and the gfx950 kernels of libmgrit.
+//
+// Layout in HBM: every space-time array is row-major [time level][n_x] FP64.
+// A relaxation launch processes `nint` coarse intervals, one workgroup each
+// (the time-parallel dimension of MGRIT, Sec. 2.2); the spatial state of an
+// interval stays on-chip (registers or LDS) for all of its fine steps.
+#pragma once
+
+#include <stdint.h>
+
+namespace mgr {
+
+// What a relaxation launch writes (Sec. 2.2 terminology).
+enum RelaxMode : int {
+  MODE_FC = 0,   // F- then C-relaxation: out[j+out_off] = Phi^m start_j (+g)
+  MODE_RES = 1,  // F-relaxation + C-point residual: out[j+1] = g + Phi^m start_j - ref[j+1]
+  MODE_F = 2,    // F-relaxation writing every point: out[j*m + s], s = 0..m-1
+                 // (the extra block j == nint writes its start state only)
+};
+
+// How the right-hand side g of the level's system enters the steps.
+enum RhsMode : int {
+  RHS_NONE = 0,    // g = 0 (fine level)
+  RHS_EVERY = 1,   // g^{jm+s} added after step s (rows of `rhs`, coarse levels)
+  RHS_CPOINT = 2,  // g only at C-points: rhs[j+1] added after step m
+};
+
+struct RelaxArgs {
+  // start state of interval j: in[j*in_stride] (+ corr[j*corr_stride]); zero if zero_in
+  const double* in;
+  long long in_stride;     // in rows
+  const double* corr;
+  long long corr_stride;   // in rows
+  const double* rhs;
+  const double* ref;       // MODE_RES: the C-points v being tested
+  double* out;
+  double* partial;         // MODE_RES: sum of r^2 per interval (may be null)
+  const double* taps;      // stencil: weights of the window offsets omin..omin+W-1
+  const int* tap_off;      // generic kernel: offsets in [0, nx)
+  const void* sdirk;       // SDIRK kernel: device SdirkDev
+  int ntaps;               // generic kernel: number of taps
+  int omin;                // stencil window start (frame shift per step), in [0, nx)
+  int mode, rhs_mode;
+  int m;                   // fine steps per interval
+  int nx;
+  int nint;                // number of intervals (blocks of MODE_FC/MODE_RES)
+  int zero_in;             // start from zero instead of `in`
+  int write_row0;          // MODE_FC: block 0 also writes out[0] = start_0
+  int out_off;             // MODE_FC: out row of interval j is j + out_off
+  int write_last;          // MODE_F: also write the state after step m
+};
+
+// One factor of a cyclic banded stage solve: a linear recurrence of order
+// <= 2 run forward (dir = +1: y_i = x_i + a1 y_{i-1} + a2 y_{i-2}) or
+// backward (dir = -1: y_i = x_i + a1 y_{i+1} + a2 y_{i+2}), periodic in i.
+// The constants of its chunked scan over lanes (chunk length K, NL lanes):
+// Hp[d] = H^(2^d) with H the 2x2 chunk transfer matrix, and
+// Cinv = (I - H^NL)^{-1} (cyclic closure).  2x2 matrices are row-major.
+constexpr int MAX_FACTORS = 4;
+constexpr int MAX_STAGES = 6;
+struct RecDev {
+  int dir;
+  int pad_;
+  double a1, a2;
+  double Hp[11][4];
+  double Cinv[4];
+};
+
+// SDIRK step data (Appendix A, Table 8): stage matrix M = I - gamma dt L is
+// applied as M^{-1} = scale * prod_f (factor f)^{-1}.
+struct SdirkDev {
+  int s;                 // stages
+  int nf;                // recurrence factors
+  int K;                 // chunk length the scan constants were built for
+  int NL;                // lanes the scan constants were built for
+  double A[MAX_STAGES][MAX_STAGES];
+  double b[MAX_STAGES];
+  double inv_gamma;      // 1/gamma: dt L Y_i = (Y_i - rhs_i)/gamma
+  double scale;          // 1/K of the factorization
+  RecDev f[MAX_FACTORS];
+};
+
+}  // namespace mgr

@@ -1,0 +1,840 @@
+// libmgrit host runtime: plans, the MGRIT cycle driver and the C-ABI of
+// include/mgrit.h.  Every step of a solve runs in the kernels of
+// relax_kernels.h / misc.hip on the plan's HIP stream; this file only
+// sequences launches, keeps the level hierarchy and reads back one FP64
+// norm per iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mgrit.h"
+#include "plan.h"
+#include "registry.h"
+#include "setup.h"
+
+namespace mgr {
+
+// ---------------------------------------------------------------------------
+// kernel selection
+// ---------------------------------------------------------------------------
+static bool pick_stencil_shape(int nx, int Wb, bool seq, int& K, int& NL) {
+  // lanes own K contiguous points, NL = nx/K lanes, a multiple of 64 and at
+  // most 256 (one workgroup).  Interval relaxation prefers K = 16 (enough
+  // independent FMAs per lane, halo amortized); the single-workgroup
+  // sequential sweep prefers NL = 256 (one wavefront per SIMD of the CU).
+  int bestK = -1, bestNL = 0;
+  double best = 1e30;
+  for (int i = 0; i < kNumK; ++i) {
+    const int k = kKs[i];
+    if (nx % k) continue;
+    const int nl = nx / k;
+    if (nl % 64 || nl > 256 || nl < 64) continue;
+    if (Wb - 1 > nx) continue;
+    double score = seq ? std::fabs(std::log2((double)nl) - 8.0)
+                       : std::fabs(std::log2((double)k) - 4.0);
+    if (score < best) {
+      best = score;
+      bestK = k;
+      bestNL = nl;
+    }
+  }
+  if (bestK < 0) return false;
+  K = bestK;
+  NL = bestNL;
+  return true;
+}
+
+static int pick_width(int W) {
+  for (int i = 0; i < kNumWidths; ++i)
+    if (kWidths[i] >= W) return kWidths[i];
+  return -1;
+}
+
+int OpDesc::init_stencil(const Taps& t, int nx, bool seq, std::string& err) {
+  const KernelTable& kt = kernel_table();
+  nnz = (int)t.off.size();
+  std::vector<double> dense;
+  int W = 1;
+  tap_window(t, nx, omin, W, dense);
+  width = W;
+  const int Wb = pick_width(W);
+  int k = 0, nl = 0;
+  if (Wb > 0 && pick_stencil_shape(nx, Wb, seq, k, nl)) {
+    kind = OP_STENCIL;
+    K = k;
+    NL = nl;
+    Wbucket = Wb;
+    const int ki = k_index(K), wi = width_index(Wb);
+    fn[0] = kt.stencil[0][ki][wi];
+    fn[1] = kt.stencil[1][ki][wi];
+    dense.resize(Wb, 0.0);
+    const int H = std::min(Wb - 1, K);
+    const bool shfl = (Wb - 1 <= K);
+    for (int p = 0; p < 2; ++p) {
+      const size_t el = p == 0 ? sizeof(double) : sizeof(float);
+      shmem[p] = shfl ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el
+                      : 2 * (size_t)H * NL * el;
+    }
+    if (hipMalloc(&d_taps, dense.size() * sizeof(double)) != hipSuccess) return MGRIT_ENOMEM;
+    bytes += dense.size() * sizeof(double);
+    if (hipMemcpy(d_taps, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return MGRIT_EHIP;
+  } else {
+    // generic LDS kernel: state of 2 n_x values in LDS
+    if ((size_t)2 * nx * sizeof(double) > 160 * 1024) {
+      err = "n_x too large for the generic relaxation kernel";
+      return MGRIT_EINVAL;
+    }
+    kind = OP_GENERIC;
+    NL = 256;
+    fn[0] = kt.generic[0];
+    fn[1] = kt.generic[1];
+    shmem[0] = (size_t)2 * nx * sizeof(double);
+    shmem[1] = (size_t)2 * nx * sizeof(float);
+    std::vector<int> off;
+    std::vector<double> w;
+    for (int q = 0; q < W; ++q)
+      if (dense[q] != 0.0) {
+        off.push_back((omin + q) % nx);
+        w.push_back(dense[q]);
+      }
+    ntaps = (int)off.size();
+    omin = 0;
+    if (hipMalloc(&d_taps, std::max<size_t>(1, w.size()) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_off, std::max<size_t>(1, off.size()) * sizeof(int)) != hipSuccess)
+      return MGRIT_ENOMEM;
+    bytes += w.size() * (sizeof(double) + sizeof(int));
+    if (hipMemcpy(d_taps, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return MGRIT_EHIP;
+  }
+  for (int p = 0; p < 2; ++p)
+    if (fn[p] && shmem[p] > 64 * 1024)
+      if (hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shmem[p]) != hipSuccess)
+        return MGRIT_EHIP;
+  return MGRIT_OK;
+}
+
+int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
+  const KernelTable& kt = kernel_table();
+  // lanes: NL = nx/K, multiple of 64, at most 512; prefer NL = 256
+  int bestK = -1;
+  double best = 1e30;
+  for (int i = 0; i < kNumSdirkK; ++i) {
+    const int k = kSdirkKs[i];
+    if (nx % k) continue;
+    const int nl = nx / k;
+    if (nl % 64 || nl > 512) continue;
+    const double score = std::fabs(std::log2((double)nl) - 8.0) + (nl > 256 ? 0.5 : 0.0);
+    if (score < best) {
+      best = score;
+      bestK = k;
+    }
+  }
+  if (bestK < 0) {
+    err = "SDIRK plans need n_x a multiple of 64 with n_x/K <= 512 for K <= 16";
+    return MGRIT_EINVAL;
+  }
+  K = bestK;
+  NL = nx / K;
+  SdirkDev sd;
+  if (!sdirk_setup(t, cfl, K, NL, sd, err)) return MGRIT_EINVAL;
+  const int si = sdirk_shape_index(sd.s, sd.nf);
+  if (si < 0) {
+    err = "no SDIRK kernel for this stage/factor count";
+    return MGRIT_EINVAL;
+  }
+  kind = OP_SDIRK;
+  fn[0] = kt.sdirk[0][sdirk_k_index(K)][si];
+  fn[1] = kt.sdirk[1][sdirk_k_index(K)][si];
+  shmem[0] = shmem[1] = 0;
+  nnz = 0;
+  if (hipMalloc(&d_sdirk, sizeof(SdirkDev)) != hipSuccess) return MGRIT_ENOMEM;
+  bytes += sizeof(SdirkDev);
+  if (hipMemcpy(d_sdirk, &sd, sizeof(SdirkDev), hipMemcpyHostToDevice) != hipSuccess)
+    return MGRIT_EHIP;
+  return MGRIT_OK;
+}
+
+void OpDesc::release() {
+  if (d_taps) (void)hipFree(d_taps);
+  if (d_off) (void)hipFree(d_off);
+  if (d_sdirk) (void)hipFree(d_sdirk);
+  d_taps = nullptr;
+  d_off = nullptr;
+  d_sdirk = nullptr;
+}
+
+std::string OpDesc::describe() const {
+  char buf[160];
+  if (kind == OP_STENCIL)
+    snprintf(buf, sizeof buf, "stencil<K=%d,W=%d(of %d)> NL=%d omin=%d nnz=%d", K, Wbucket,
+             width, NL, omin, nnz);
+  else if (kind == OP_GENERIC)
+    snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
+  else
+    snprintf(buf, sizeof buf, "sdirk<K=%d> NL=%d", K, NL);
+  return buf;
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+static RelaxArgs base_args(const Plan& P, const OpDesc& op) {
+  RelaxArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.taps = op.d_taps;
+  a.tap_off = op.d_off;
+  a.sdirk = op.d_sdirk;
+  a.ntaps = op.ntaps;
+  a.omin = op.omin;
+  a.nx = P.nx;
+  a.in_stride = 1;
+  a.corr_stride = 1;
+  return a;
+}
+
+int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int cls) {
+  KernelFn fn = op.fn[prec];
+  if (!fn) return MGRIT_EINVAL;
+  RelaxArgs args = a;
+  void* kargs[] = {&args};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (profiling) {
+    e0 = take_event();
+    (void)hipEventRecord(e0, stream);
+  }
+  hipError_t st = hipLaunchKernel((const void*)fn, dim3(grid), dim3(op.NL), kargs,
+                                  op.shmem[prec], stream);
+  if (st != hipSuccess) return MGRIT_EHIP;
+  if (profiling) {
+    e1 = take_event();
+    (void)hipEventRecord(e1, stream);
+    pending.push_back({cls, e0, e1});
+  }
+  return MGRIT_OK;
+}
+
+hipEvent_t Plan::take_event() {
+  if (event_pool.empty()) {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  hipEvent_t e = event_pool.back();
+  event_pool.pop_back();
+  return e;
+}
+
+void Plan::collect_profile() {
+  for (auto& p : pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.e0, p.e1);
+    prof.ms[p.cls] += ms;
+    prof.launches[p.cls] += 1;
+    event_pool.push_back(p.e0);
+    event_pool.push_back(p.e1);
+  }
+  pending.clear();
+}
+
+int Plan::mark_util(int cls, hipEvent_t& e0) {
+  if (!profiling) return MGRIT_OK;
+  e0 = take_event();
+  (void)hipEventRecord(e0, stream);
+  (void)cls;
+  return MGRIT_OK;
+}
+
+void Plan::end_util(int cls, hipEvent_t e0) {
+  if (!profiling) return;
+  hipEvent_t e1 = take_event();
+  (void)hipEventRecord(e1, stream);
+  pending.push_back({cls, e0, e1});
+}
+
+// Relaxation on level l (0 = fine).  mode: MODE_FC / MODE_RES / MODE_F.
+int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride,
+                const double* corr, const double* rhs, int rhs_mode, double* out,
+                double* partial, int steps) {
+  Level& L = lev[l];
+  const OpDesc& op = L.op;
+  RelaxArgs a = base_args(*this, op);
+  a.in = in;
+  a.in_stride = in_stride;
+  a.zero_in = in == nullptr;
+  a.corr = corr;
+  a.rhs = rhs;
+  a.rhs_mode = rhs ? rhs_mode : RHS_NONE;
+  a.mode = mode;
+  a.m = steps;
+  a.nint = L.nc;
+  a.out = out;
+  if (mode == MODE_FC) {
+    a.out_off = 1;
+    a.write_row0 = 1;
+  } else if (mode == MODE_RES) {
+    a.ref = in;
+    a.partial = partial;
+  }
+  const int grid = L.nc + (mode == MODE_F ? 1 : 0);
+  if (l == 0) fine_dof_steps += (double)L.nc * steps * nx;
+  return launch(op, prec, a, grid, l == 0 ? MGRIT_PROF_RELAX_FINE
+                                          : (mode == MODE_F ? MGRIT_PROF_OTHER
+                                                            : MGRIT_PROF_RELAX_COARSE));
+}
+
+// v^j = u^j (+ e^j) for j = 0..nc: the C-points of F-relaxation-only
+// (Parareal) iterations, by a zero-step pass.
+int Plan::copy_cpoints(int l, int prec, const double* in, long long in_stride,
+                       const double* corr, double* out) {
+  Level& L = lev[l];
+  const OpDesc& op = L.op;
+  RelaxArgs a = base_args(*this, op);
+  a.in = in;
+  a.in_stride = in_stride;
+  a.zero_in = in == nullptr;
+  a.corr = corr;
+  a.mode = MODE_FC;
+  a.m = 0;
+  a.nint = L.nc + 1;
+  a.out = out;
+  a.out_off = 0;
+  return launch(op, prec, a, L.nc + 1, MGRIT_PROF_OTHER);
+}
+
+// Coarsest level: x^0 = g^0 = 0, x^{n+1} = Phi_L x^n + g^{n+1}, all points.
+// Always FP64 (the sequential coarse solve stays FP64 in every precision).
+int Plan::sequential(const double* g) {
+  Level& L = lev.back();
+  const OpDesc& op = L.seq;
+  RelaxArgs a = base_args(*this, op);
+  a.zero_in = 1;
+  a.rhs = g;
+  a.rhs_mode = RHS_EVERY;
+  a.mode = MODE_F;
+  a.m = L.n;
+  a.nint = 1;
+  a.write_last = 1;
+  a.out = L.X;
+  return launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
+}
+
+int Plan::norm(const double* partial, int n, double& value) {
+  hipEvent_t e0 = nullptr;
+  mark_util(MGRIT_PROF_NORM, e0);
+  launch_norm_reduce(partial, n, scale * scale, d_norm, stream);
+  end_util(MGRIT_PROF_NORM, e0);
+  if (hipMemcpyAsync(h_norm, d_norm, sizeof(double), hipMemcpyDeviceToHost, stream) !=
+      hipSuccess)
+    return MGRIT_EHIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return MGRIT_EHIP;
+  value = *h_norm;
+  return MGRIT_OK;
+}
+
+// Solve level l's error system (rhs g, zero initial guess) into lev[l].X.
+int Plan::coarse_solve(int l, const double* g, int kind, int prec) {
+  if (l == (int)lev.size() - 1) return sequential(g);
+  int rc;
+  if (kind == MGRIT_CYCLE_F) {
+    if ((rc = cycle(l, g, true, MGRIT_CYCLE_F, prec))) return rc;
+    return cycle(l, g, false, MGRIT_CYCLE_V, prec);
+  }
+  return cycle(l, g, true, MGRIT_CYCLE_V, prec);
+}
+
+// One V- or F-cycle on level l >= 1 (Sec. 4.4): relax, residual, coarse
+// solve, correct + F-relax.  Guess: lev[l].X (all points) unless `zero`.
+int Plan::cycle(int l, const double* g, bool zero, int kind, int prec) {
+  Level& L = lev[l];
+  int rc;
+  const double* guess = zero ? nullptr : L.X;
+  if (relax_kind == MGRIT_RELAX_FCF) {
+    if ((rc = relax(l, prec, MODE_FC, guess, m, nullptr, g, RHS_EVERY, L.V, nullptr, m)))
+      return rc;
+  } else {
+    // F-relaxation only: v = u
+    if ((rc = copy_cpoints(l, prec, guess, m, nullptr, L.V))) return rc;
+  }
+  if ((rc = relax(l, prec, MODE_RES, L.V, 1, nullptr, g, RHS_EVERY, L.R, nullptr, m))) return rc;
+  if ((rc = coarse_solve(l + 1, L.R, kind, prec))) return rc;
+  return relax(l, prec, MODE_F, L.V, 1, lev[l + 1].X, g, RHS_EVERY, L.X, nullptr, m);
+}
+
+}  // namespace mgr
+
+using namespace mgr;
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mgrit_version(void) { return 100; }
+
+const char* mgrit_strerror(int code) {
+  switch (code) {
+    case MGRIT_OK: return "success";
+    case MGRIT_EINVAL: return "invalid argument or unsupported shape";
+    case MGRIT_EUNSTABLE: return "Courant number above the CFL limit of the explicit scheme";
+    case MGRIT_ENOMEM: return "allocation failed";
+    case MGRIT_EHIP: return "HIP runtime error";
+    case MGRIT_ENOTCONV: return "maximum iterations reached above tolerance";
+    case MGRIT_EDIVERGED: return "non-finite residual norm";
+    case MGRIT_EIMAG: return "least-squares solution has imaginary part above 1e-8";
+    case MGRIT_ENODEV: return "no usable gfx950 device";
+    case MGRIT_ECAPACITY: return "output arrays too small";
+    case MGRIT_EBUSY: return "admission refused: HBM budget";
+    default: return "unknown error";
+  }
+}
+
+int mgrit_max_amplification(int scheme, double cfl, double* amp) {
+  Tableau t;
+  if (!amp || !get_tableau(scheme, t) || !(cfl > 0.0)) return MGRIT_EINVAL;
+  *amp = max_amplification(t, cfl);
+  return MGRIT_OK;
+}
+
+int mgrit_phi_taps(int scheme, double cfl, int nx, int capacity, int* offsets,
+                   double* weights, int* nnz) {
+  Tableau t;
+  if (!get_tableau(scheme, t) || nx < 1 || !nnz || !(cfl > 0.0)) return MGRIT_EINVAL;
+  if (t.implicit) return MGRIT_EINVAL;
+  Taps tp;
+  erk_taps(t, cfl, nx, tp);
+  *nnz = (int)tp.off.size();
+  if ((int)tp.off.size() > capacity) return MGRIT_ECAPACITY;
+  if (!offsets || !weights) return MGRIT_EINVAL;
+  for (size_t i = 0; i < tp.off.size(); ++i) {
+    offsets[i] = tp.off[i];
+    weights[i] = tp.w[i];
+  }
+  return MGRIT_OK;
+}
+
+int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels, int rule,
+                       const int* widths, double eta, mgrit_taps* out, double* max_imag) {
+  if (!out) return MGRIT_EINVAL;
+  std::vector<Taps> h;
+  double mi = 0.0;
+  int rc;
+  try {
+    rc = psi_hierarchy(scheme, cfl, nx, m, levels, rule, widths, eta, h, mi);
+  } catch (...) {
+    return MGRIT_ENOMEM;
+  }
+  if (rc != MGRIT_OK && rc != MGRIT_EIMAG) return rc;
+  if (max_imag) *max_imag = mi;
+  for (int l = 0; l < levels - 1; ++l) {
+    const Taps& t = h[l];
+    if ((int)t.off.size() > out[l].nnz || !out[l].offset || !out[l].weight) {
+      out[l].nnz = (int)t.off.size();
+      return MGRIT_ECAPACITY;
+    }
+    out[l].nnz = (int)t.off.size();
+    for (size_t i = 0; i < t.off.size(); ++i) {
+      out[l].offset[i] = t.off[i];
+      out[l].weight[i] = t.w[i];
+    }
+  }
+  return rc;
+}
+
+static int check_device() {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return MGRIT_ENODEV;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGRIT_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MGRIT_ENODEV;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MGRIT_ENODEV;
+  return MGRIT_OK;
+}
+
+int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
+                      int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
+                      int relax, int precision, void* hip_stream) {
+  if (!out) return MGRIT_EINVAL;
+  *out = nullptr;
+  Tableau t;
+  if (!get_tableau(scheme, t) || nx < 2 || nt < 1 || m < 2 || levels < 2 ||
+      !(alpha > 0.0) || !(cfl > 0.0) || !psi)
+    return MGRIT_EINVAL;
+  if (cycle != MGRIT_CYCLE_V && cycle != MGRIT_CYCLE_F) return MGRIT_EINVAL;
+  if (relax != MGRIT_RELAX_FCF && relax != MGRIT_RELAX_F) return MGRIT_EINVAL;
+  if (precision != MGRIT_FP64 && precision != MGRIT_FP32_RELAX) return MGRIT_EINVAL;
+  long long span = 1;
+  for (int l = 1; l < levels; ++l) span *= m;
+  if (span > nt || nt % span) return MGRIT_EINVAL;
+  for (int l = 0; l < levels - 1; ++l)
+    if (psi[l].nnz < 1 || !psi[l].offset || !psi[l].weight) return MGRIT_EINVAL;
+  if (!t.implicit && max_amplification(t, cfl) > 1.0 + 1e-6) return MGRIT_EUNSTABLE;
+  int rc = check_device();
+  if (rc) return rc;
+
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return MGRIT_ENOMEM;
+  P->nx = nx;
+  P->nt = nt;
+  P->m = m;
+  P->scheme = scheme;
+  P->alpha = alpha;
+  P->cfl = cfl;
+  P->cycle_kind = cycle;
+  P->relax_kind = relax;
+  P->precision = precision;
+  P->dx = 2.0 / nx;
+  P->dt = cfl * P->dx / alpha;
+  P->scale = std::sqrt(P->dx * P->dt);
+  P->stream = (hipStream_t)hip_stream;
+  std::string err;
+  auto fail = [&](int code) {
+    mgrit_destroy(reinterpret_cast<mgrit_plan_t>(P));
+    return code;
+  };
+  try {
+    P->lev.resize(levels);
+    long long n = nt;
+    for (int l = 0; l < levels; ++l) {
+      Level& L = P->lev[l];
+      L.n = (int)n;
+      L.nc = (l < levels - 1) ? (int)(n / m) : 0;
+      if (l == 0) {
+        if (t.implicit) rc = L.op.init_sdirk(t, cfl, nx, err);
+        else {
+          Taps f;
+          erk_taps(t, cfl, nx, f);
+          rc = L.op.init_stencil(f, nx, false, err);
+        }
+      } else {
+        Taps f;
+        f.off.assign(psi[l - 1].offset, psi[l - 1].offset + psi[l - 1].nnz);
+        f.w.assign(psi[l - 1].weight, psi[l - 1].weight + psi[l - 1].nnz);
+        if (l < levels - 1) rc = L.op.init_stencil(f, nx, false, err);
+        else rc = L.seq.init_stencil(f, nx, true, err);
+      }
+      if (rc) return fail(rc);
+      P->bytes += L.op.bytes + L.seq.bytes;
+      n /= m;
+    }
+    // device buffers
+    auto alloc = [&](double** p, long long rows) {
+      size_t b = (size_t)rows * nx * sizeof(double);
+      if (hipMalloc((void**)p, b) != hipSuccess) return false;
+      P->bytes += b;
+      return true;
+    };
+    const long long nc = nt / m;
+    if (!alloc(&P->Va, nc + 1) || !alloc(&P->Vb, nc + 1) || !alloc(&P->lev[0].R, nc + 1))
+      return fail(MGRIT_ENOMEM);
+    if (precision == MGRIT_FP32_RELAX && (!alloc(&P->U, nc + 1) || !alloc(&P->Rout, nc + 1)))
+      return fail(MGRIT_ENOMEM);
+    for (int l = 1; l < levels; ++l) {
+      Level& L = P->lev[l];
+      if (!alloc(&L.X, L.n + 1)) return fail(MGRIT_ENOMEM);
+      if (l < levels - 1 && (!alloc(&L.V, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
+        return fail(MGRIT_ENOMEM);
+    }
+    if (hipMalloc((void**)&P->partial, (size_t)(nc + 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&P->d_norm, sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&P->h_norm, sizeof(double)) != hipSuccess)
+      return fail(MGRIT_ENOMEM);
+    P->bytes += (size_t)(nc + 2) * sizeof(double);
+    std::string d;
+    for (int l = 0; l < levels; ++l) {
+      const OpDesc& o = (l == levels - 1) ? P->lev[l].seq : P->lev[l].op;
+      char hdr[64];
+      snprintf(hdr, sizeof hdr, "L%d n=%d: ", l + 1, P->lev[l].n);
+      d += hdr + o.describe() + (l + 1 < levels ? "; " : "");
+    }
+    P->description = d;
+  } catch (...) {
+    return fail(MGRIT_ENOMEM);
+  }
+  *out = reinterpret_cast<mgrit_plan_t>(P);
+  return MGRIT_OK;
+}
+
+void mgrit_destroy(mgrit_plan_t plan) {
+  if (!plan) return;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& L : P->lev) {
+    L.op.release();
+    L.seq.release();
+    if (L.X) (void)hipFree(L.X);
+    if (L.V) (void)hipFree(L.V);
+    if (L.R) (void)hipFree(L.R);
+  }
+  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm})
+    if (p) (void)hipFree(p);
+  if (P->h_norm) (void)hipHostFree(P->h_norm);
+  for (auto& p : P->pending) {
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+  }
+  for (auto e : P->event_pool) (void)hipEventDestroy(e);
+  delete P;
+}
+
+int mgrit_plan_bytes(mgrit_plan_t plan, size_t* b) {
+  if (!plan || !b) return MGRIT_EINVAL;
+  *b = reinterpret_cast<Plan*>(plan)->bytes;
+  return MGRIT_OK;
+}
+
+int mgrit_plan_set_seed(mgrit_plan_t plan, unsigned long long seed) {
+  if (!plan) return MGRIT_EINVAL;
+  reinterpret_cast<Plan*>(plan)->seed = seed;
+  return MGRIT_OK;
+}
+
+int mgrit_get_stats(mgrit_plan_t plan, mgrit_stats* s) {
+  if (!plan || !s) return MGRIT_EINVAL;
+  *s = reinterpret_cast<Plan*>(plan)->stats;
+  return MGRIT_OK;
+}
+
+int mgrit_set_profiling(mgrit_plan_t plan, int enable) {
+  if (!plan) return MGRIT_EINVAL;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  P->collect_profile();
+  P->profiling = enable != 0;
+  if (enable) {
+    std::memset(&P->prof, 0, sizeof P->prof);
+    P->prof_dof_base = P->fine_dof_steps;
+  }
+  return MGRIT_OK;
+}
+
+int mgrit_get_profile(mgrit_plan_t plan, mgrit_profile* prof) {
+  if (!plan || !prof) return MGRIT_EINVAL;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  P->collect_profile();
+  *prof = P->prof;
+  prof->fine_dof_steps = P->fine_dof_steps - P->prof_dof_base;
+  return MGRIT_OK;
+}
+
+int mgrit_operator_complexity(mgrit_plan_t plan, double* oc) {
+  if (!plan || !oc) return MGRIT_EINVAL;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  // eq. (10); the fine SDIRK stepper has no finite nnz: report NaN
+  const int L = (int)P->lev.size();
+  double n1 = P->lev[0].op.nnz;
+  if (n1 <= 0) {
+    *oc = NAN;
+    return MGRIT_OK;
+  }
+  double s = 0.0, f = 1.0;
+  for (int l = 0; l < L; ++l) {
+    const OpDesc& o = (l == L - 1) ? P->lev[l].seq : P->lev[l].op;
+    s += f * o.nnz;
+    f /= P->m;
+  }
+  *oc = s / n1;
+  return MGRIT_OK;
+}
+
+const char* mgrit_plan_describe(mgrit_plan_t plan) {
+  if (!plan) return "";
+  return reinterpret_cast<Plan*>(plan)->description.c_str();
+}
+
+int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
+                    int ksteps) {
+  if (!plan || !in || !out || batch < 0 || ksteps < 0) return MGRIT_EINVAL;
+  if (batch == 0) return MGRIT_OK;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  const OpDesc& op = P->lev[0].op;
+  RelaxArgs a = base_args(*P, op);
+  a.in = in;
+  a.mode = MODE_FC;
+  a.m = ksteps;
+  a.nint = batch;
+  a.out = out;
+  a.out_off = 0;
+  const int prec = P->precision == MGRIT_FP32_RELAX ? 1 : 0;
+  return P->launch(op, prec, a, batch, MGRIT_PROF_RELAX_FINE);
+}
+
+// ---- the solve ---------------------------------------------------------
+static int finish_output(Plan* P, const double* C, double* u_out, int out_kind) {
+  const int nx = P->nx, nc = P->nt / P->m;
+  const size_t row = (size_t)nx * sizeof(double);
+  switch (out_kind) {
+    case MGRIT_OUT_NONE: return MGRIT_OK;
+    case MGRIT_OUT_FINAL:
+      return hipMemcpyAsync(u_out, C + (size_t)nc * nx, row, hipMemcpyDeviceToDevice,
+                            P->stream) == hipSuccess ? MGRIT_OK : MGRIT_EHIP;
+    case MGRIT_OUT_CPOINTS:
+      return hipMemcpyAsync(u_out, C, row * (nc + 1), hipMemcpyDeviceToDevice, P->stream) ==
+                     hipSuccess ? MGRIT_OK : MGRIT_EHIP;
+    case MGRIT_OUT_ALL:
+      // F-relaxation of the converged C-points on the fine level, in FP64
+      return P->relax(0, 0, MODE_F, C, 1, nullptr, nullptr, RHS_NONE, u_out, nullptr, P->m);
+    default: return MGRIT_EINVAL;
+  }
+}
+
+static int init_iterate(Plan* P, const double* u0, const double* uinit, double* dst) {
+  const int nx = P->nx, nc = P->nt / P->m;
+  const size_t row = (size_t)nx * sizeof(double);
+  if (uinit) {
+    if (hipMemcpyAsync(dst, uinit, row * (nc + 1), hipMemcpyDeviceToDevice, P->stream) !=
+        hipSuccess)
+      return MGRIT_EHIP;
+  } else {
+    launch_uniform_init(dst, nc + 1, nx, P->seed, P->stream);
+  }
+  return hipMemcpyAsync(dst, u0, row, hipMemcpyDeviceToDevice, P->stream) == hipSuccess
+             ? MGRIT_OK : MGRIT_EHIP;
+}
+
+static int solve_fp64(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
+                      double* u_out, int out_kind, double* hist, int* iters) {
+  const int nc = P->nt / P->m;
+  int rc = init_iterate(P, u0, uinit, P->Va);
+  if (rc) return rc;
+  double* cur = P->Va;
+  double* nxt = P->Vb;
+  const double* corr = nullptr;
+  int status = MGRIT_ENOTCONV;
+  int it = 0;
+  for (;; ++it) {
+    if (P->relax_kind == MGRIT_RELAX_FCF) {
+      if ((rc = P->relax(0, 0, MODE_FC, cur, 1, corr, nullptr, RHS_NONE, nxt, nullptr, P->m)))
+        return rc;
+      P->stats.fine_passes_fp64 += 1;
+    } else if ((rc = P->copy_cpoints(0, 0, cur, 1, corr, nxt))) {
+      return rc;
+    }
+    if ((rc = P->relax(0, 0, MODE_RES, nxt, 1, nullptr, nullptr, RHS_NONE, P->lev[0].R,
+                       P->partial, P->m)))
+      return rc;
+    P->stats.fine_passes_fp64 += 1;
+    double res = 0.0;
+    if ((rc = P->norm(P->partial, nc, res))) return rc;
+    if (hist) hist[it] = res;
+    P->stats.final_residual = res;
+    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
+    if (res <= tol) { status = MGRIT_OK; break; }
+    if (it >= maxit) { status = MGRIT_ENOTCONV; break; }
+    if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 0))) return rc;
+    corr = P->lev[1].X;
+    std::swap(cur, nxt);
+  }
+  P->stats.iterations = it;
+  if (iters) *iters = it;
+  if ((rc = finish_output(P, nxt, u_out, out_kind))) return rc;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
+  return status;
+}
+
+// FP32 relaxation inside FP64 iterative refinement: the FP64 residual r of
+// the iterate u, inner MGRIT cycles with FP32 relaxation on the error
+// system e^{j+1} = Phi^m e^j + r^{j+1} (sequential coarse solve, residual
+// subtraction and norms in FP64), then u += e in FP64.
+static int solve_ir(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
+                    double* u_out, int out_kind, double* hist, int* iters) {
+  const int nc = P->nt / P->m;
+  const long long cells = (long long)(nc + 1) * P->nx;
+  int rc = init_iterate(P, u0, uinit, P->U);
+  if (rc) return rc;
+  int status = MGRIT_ENOTCONV;
+  int outer = 0, inner_total = 0;
+  const double kInnerDrop = 1e-5;  // inner solve target relative to |r|
+  const int kInnerMax = 8;
+  for (;; ++outer) {
+    if ((rc = P->relax(0, 0, MODE_RES, P->U, 1, nullptr, nullptr, RHS_NONE, P->Rout,
+                       P->partial, P->m)))
+      return rc;
+    P->stats.fine_passes_fp64 += 1;
+    double res = 0.0;
+    if ((rc = P->norm(P->partial, nc, res))) return rc;
+    if (hist) hist[outer] = res;
+    P->stats.final_residual = res;
+    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
+    if (res <= tol) { status = MGRIT_OK; break; }
+    if (outer >= maxit) { status = MGRIT_ENOTCONV; break; }
+    double* cur = P->Va;
+    double* nxt = P->Vb;
+    const double* corr = nullptr;
+    double prev = res;
+    for (int k = 0;; ++k) {
+      if (P->relax_kind == MGRIT_RELAX_FCF) {
+        if ((rc = P->relax(0, 1, MODE_FC, k == 0 ? nullptr : cur, 1, corr, P->Rout,
+                           RHS_CPOINT, nxt, nullptr, P->m)))
+          return rc;
+        P->stats.fine_passes_fp32 += 1;
+      } else if ((rc = P->copy_cpoints(0, 1, k == 0 ? nullptr : cur, 1, corr, nxt))) {
+        return rc;
+      }
+      if ((rc = P->relax(0, 1, MODE_RES, nxt, 1, nullptr, P->Rout, RHS_CPOINT, P->lev[0].R,
+                         P->partial, P->m)))
+        return rc;
+      P->stats.fine_passes_fp32 += 1;
+      double rho = 0.0;
+      if ((rc = P->norm(P->partial, nc, rho))) return rc;
+      if (!std::isfinite(rho)) { status = MGRIT_EDIVERGED; break; }
+      // stop at the target, at the cap, or once a coarse correction stops
+      // halving the inner residual (FP32 rounding floor)
+      const bool done = rho <= kInnerDrop * res || k + 1 >= kInnerMax ||
+                        (k >= 1 && rho > 0.5 * prev);
+      prev = rho;
+      if (done) break;
+      if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 1))) return rc;
+      ++inner_total;
+      corr = P->lev[1].X;
+      std::swap(cur, nxt);
+    }
+    if (status == MGRIT_EDIVERGED) break;
+    // u += e (the FCF-relaxed inner iterate whose residual was tested)
+    hipEvent_t e0 = nullptr;
+    P->mark_util(MGRIT_PROF_OTHER, e0);
+    launch_axpy(P->U, nxt, cells, P->stream);
+    P->end_util(MGRIT_PROF_OTHER, e0);
+    ++inner_total;
+  }
+  P->stats.iterations = inner_total;
+  P->stats.outer_iterations = outer;
+  if (iters) *iters = inner_total;
+  if ((rc = finish_output(P, P->U, u_out, out_kind))) return rc;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
+  return status;
+}
+
+int mgrit_solve(mgrit_plan_t plan, const double* u0, const double* uinit, double tol,
+                int maxit, double* u_out, int out_kind, double* hist, int* iters) {
+  if (!plan || !u0 || maxit < 0 || !(tol >= 0.0)) return MGRIT_EINVAL;
+  if (out_kind != MGRIT_OUT_NONE && !u_out) return MGRIT_EINVAL;
+  if (out_kind < MGRIT_OUT_NONE || out_kind > MGRIT_OUT_ALL) return MGRIT_EINVAL;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  std::memset(&P->stats, 0, sizeof P->stats);
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = P->precision == MGRIT_FP32_RELAX
+               ? solve_ir(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
+               : solve_fp64(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters);
+  auto t1 = std::chrono::steady_clock::now();
+  P->stats.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return rc;
+}
+
+}  // extern "C"

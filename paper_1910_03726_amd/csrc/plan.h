@@ -1,0 +1,88 @@
+// Internal plan structures of libmgrit (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mgrit.h"
+#include "common.h"
+#include "registry.h"
+#include "setup.h"
+
+namespace mgr {
+
+enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
+
+// The relaxation operator of one level and the kernels that apply it.
+struct OpDesc {
+  int kind = OP_GENERIC;
+  KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
+  size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
+  int NL = 0, K = 0;                    // lanes per workgroup, points per lane
+  int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
+  int ntaps = 0, nnz = 0;
+  double* d_taps = nullptr;
+  int* d_off = nullptr;
+  void* d_sdirk = nullptr;
+  size_t bytes = 0;
+
+  int init_stencil(const Taps& t, int nx, bool seq, std::string& err);
+  int init_sdirk(const Tableau& t, double cfl, int nx, std::string& err);
+  void release();
+  std::string describe() const;
+};
+
+struct Level {
+  int n = 0;         // time steps on this level
+  int nc = 0;        // coarse intervals (n / m), 0 on the coarsest level
+  OpDesc op;         // relaxation operator (levels < L)
+  OpDesc seq;        // coarsest level: single-workgroup sequential sweep
+  double* X = nullptr;  // levels >= 2: all n+1 points (solution / correction)
+  double* V = nullptr;  // levels >= 2 (not coarsest): relaxed C-points
+  double* R = nullptr;  // C-point residuals = right-hand side of level l+1
+};
+
+struct ProfPending {
+  int cls;
+  hipEvent_t e0, e1;
+};
+
+struct Plan {
+  int nx = 0, nt = 0, m = 0, scheme = 0;
+  int cycle_kind = 0, relax_kind = 0, precision = 0;
+  double alpha = 1.0, cfl = 0.0, dx = 0.0, dt = 0.0, scale = 0.0;
+  hipStream_t stream = nullptr;
+  std::vector<Level> lev;
+  double *Va = nullptr, *Vb = nullptr;      // fine C-point iterates (ping-pong)
+  double *U = nullptr, *Rout = nullptr;     // FP64 refinement iterate and residual
+  double *partial = nullptr, *d_norm = nullptr, *h_norm = nullptr;
+  unsigned long long seed = 1;
+  size_t bytes = 0;
+  std::string description;
+  mgrit_stats stats = {};
+  // profiling
+  bool profiling = false;
+  mgrit_profile prof = {};
+  double fine_dof_steps = 0.0, prof_dof_base = 0.0;
+  std::vector<ProfPending> pending;
+  std::vector<hipEvent_t> event_pool;
+
+  int launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int cls);
+  hipEvent_t take_event();
+  void collect_profile();
+  int mark_util(int cls, hipEvent_t& e0);
+  void end_util(int cls, hipEvent_t e0);
+  int relax(int l, int prec, int mode, const double* in, long long in_stride,
+            const double* corr, const double* rhs, int rhs_mode, double* out,
+            double* partial, int steps);
+  int copy_cpoints(int l, int prec, const double* in, long long in_stride,
+                   const double* corr, double* out);
+  int sequential(const double* g);
+  int norm(const double* partial, int n, double& value);
+  int coarse_solve(int l, const double* g, int kind, int prec);
+  int cycle(int l, const double* g, bool zero, int kind, int prec);
+};
+
+}  // namespace mgr

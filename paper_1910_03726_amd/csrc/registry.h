@@ -1,0 +1,46 @@
+// Table of the compiled relaxation kernels (host side).
+#pragma once
+
+#include "common.h"
+
+namespace mgr {
+
+typedef void (*KernelFn)(RelaxArgs);
+
+// Window widths W and chunk lengths K with a register-resident stencil
+// kernel; other shapes use the generic LDS kernel.
+#define MGR_STENCIL_WIDTHS(X) \
+  X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
+constexpr int kNumWidths = 13;
+constexpr int kWidths[kNumWidths] = {2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64};
+constexpr int kNumK = 6;
+constexpr int kKs[kNumK] = {1, 2, 4, 8, 16, 32};
+
+// SDIRK variants: chunk K and (stages S, recurrence factors NF)
+constexpr int kNumSdirkK = 5;
+constexpr int kSdirkKs[kNumSdirkK] = {1, 2, 4, 8, 16};
+constexpr int kNumSdirkShapes = 4;
+constexpr int kSdirkShapes[kNumSdirkShapes][2] = {{1, 1}, {2, 1}, {3, 2}, {5, 3}};
+
+struct KernelTable {
+  KernelFn stencil[2][kNumK][kNumWidths] = {};
+  KernelFn sdirk[2][kNumSdirkK][kNumSdirkShapes] = {};
+  KernelFn generic[2] = {};
+};
+
+// Filled once on first use; prec 0 = FP64 state, 1 = FP32 state.
+const KernelTable& kernel_table();
+
+int width_index(int W);         // index into kWidths, -1 if absent
+int k_index(int K);             // index into kKs, -1 if absent
+int sdirk_k_index(int K);
+int sdirk_shape_index(int S, int NF);
+
+// Utility kernels (misc.hip).
+void launch_norm_reduce(const double* partial, int n, double scale2, double* out,
+                        void* stream);
+void launch_axpy(double* y, const double* x, long long n, void* stream);
+void launch_uniform_init(double* out, long long rows, int nx, unsigned long long seed,
+                         void* stream);
+
+}  // namespace mgr

@@ -1,0 +1,676 @@
+// Host-side setup of libmgrit (see setup.h).  Runs once per plan.
+#include "setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+#include "../../include/mgrit.h"
+
+namespace mgr {
+
+static const double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Appendix A: Butcher tableaux
+// ---------------------------------------------------------------------------
+static void set_rows(Tableau& t, std::initializer_list<std::initializer_list<double>> rows,
+                     std::initializer_list<double> b) {
+  int i = 0;
+  for (auto& r : rows) {
+    int j = 0;
+    for (double v : r) t.A[i][j++] = v;
+    ++i;
+  }
+  t.s = (int)b.size();
+  int k = 0;
+  for (double v : b) t.b[k++] = v;
+}
+
+bool get_tableau(int scheme, Tableau& t) {
+  t = Tableau();
+  const double r2 = std::sqrt(2.0) / 2.0;
+  switch (scheme) {
+    case MGRIT_ERK1:
+      set_rows(t, {{0.0}}, {1.0});
+      break;
+    case MGRIT_ERK2:
+      set_rows(t, {{0.0}, {1.0, 0.0}}, {0.5, 0.5});
+      break;
+    case MGRIT_ERK3:
+      set_rows(t, {{0.0}, {1.0}, {0.25, 0.25}}, {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0});
+      break;
+    case MGRIT_ERK4:
+      set_rows(t, {{0.0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}},
+               {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0});
+      break;
+    case MGRIT_ERK5:
+      set_rows(t,
+               {{0.0},
+                {0.25},
+                {0.125, 0.125},
+                {0.0, 0.0, 0.5},
+                {3.0 / 16.0, -3.0 / 8.0, 3.0 / 8.0, 9.0 / 16.0},
+                {-3.0 / 7.0, 8.0 / 7.0, 6.0 / 7.0, -12.0 / 7.0, 8.0 / 7.0}},
+               {7.0 / 90.0, 0.0, 32.0 / 90.0, 12.0 / 90.0, 32.0 / 90.0, 7.0 / 90.0});
+      break;
+    case MGRIT_SDIRK1:
+      set_rows(t, {{1.0}}, {1.0});
+      break;
+    case MGRIT_SDIRK2:
+      set_rows(t, {{1.0 - r2}, {r2, 1.0 - r2}}, {r2, 1.0 - r2});
+      break;
+    case MGRIT_SDIRK3: {
+      const double z = 0.43586652150845899942;
+      const double be = (1.0 - z) / 2.0;
+      const double ga = -1.5 * z * z + 4.0 * z - 0.25;
+      const double ep = 1.5 * z * z - 5.0 * z + 1.25;
+      set_rows(t, {{z}, {be, z}, {ga, ep, z}}, {ga, ep, z});
+      break;
+    }
+    case MGRIT_SDIRK4:
+      set_rows(t,
+               {{0.25},
+                {0.5, 0.25},
+                {17.0 / 50.0, -1.0 / 25.0, 0.25},
+                {371.0 / 1360.0, -137.0 / 2720.0, 15.0 / 544.0, 0.25},
+                {25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 0.25}},
+               {25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 0.25});
+      break;
+    default:
+      return false;
+  }
+  t.implicit = scheme >= MGRIT_SDIRK1;
+  t.p = t.implicit ? scheme - 10 : scheme;
+  return true;
+}
+
+// Sec. 2.1: U1..U5.
+void upwind(int p, std::vector<int>& off, std::vector<double>& d) {
+  off.clear();
+  d.clear();
+  auto add = [&](int o, double v) { off.push_back(o); d.push_back(v); };
+  switch (p) {
+    case 1: add(0, 1.0); add(-1, -1.0); break;
+    case 2: add(0, 1.5); add(-1, -2.0); add(-2, 0.5); break;
+    case 3:
+      add(1, 2.0 / 6.0); add(0, 3.0 / 6.0); add(-1, -1.0); add(-2, 1.0 / 6.0);
+      break;
+    case 4:
+      add(1, 3.0 / 12.0); add(0, 10.0 / 12.0); add(-1, -18.0 / 12.0);
+      add(-2, 6.0 / 12.0); add(-3, -1.0 / 12.0);
+      break;
+    case 5:
+      add(2, -3.0 / 60.0); add(1, 30.0 / 60.0); add(0, 20.0 / 60.0);
+      add(-1, -1.0); add(-2, 15.0 / 60.0); add(-3, -2.0 / 60.0);
+      break;
+    default: break;
+  }
+}
+
+cd stability(const Tableau& t, cd z) {
+  // (I - zA) y = 1 by forward substitution (A is lower triangular).
+  cd y[MAX_STAGES];
+  cd acc = 0.0;
+  for (int i = 0; i < t.s; ++i) {
+    cd r = 1.0;
+    for (int j = 0; j < i; ++j) r += z * t.A[i][j] * y[j];
+    y[i] = r / (1.0 - z * t.A[i][i]);
+    acc += t.b[i] * y[i];
+  }
+  return 1.0 + z * acc;
+}
+
+cd step_symbol(const Tableau& t, double cfl, double theta) {
+  std::vector<int> off;
+  std::vector<double> d;
+  upwind(t.p, off, d);
+  cd s = 0.0;
+  for (size_t j = 0; j < off.size(); ++j)
+    s += d[j] * std::exp(cd(0.0, off[j] * theta));
+  return stability(t, -cfl * s);
+}
+
+double max_amplification(const Tableau& t, double cfl) {
+  const int n = 20001;
+  double mx = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double th = kPi * i / (n - 1);
+    mx = std::max(mx, std::abs(step_symbol(t, cfl, th)));
+  }
+  return mx;
+}
+
+// ---------------------------------------------------------------------------
+// Corollary 1: the ERK stepper as one stencil
+// ---------------------------------------------------------------------------
+bool erk_taps(const Tableau& t, double cfl, int nx, Taps& out) {
+  if (t.implicit) return false;
+  std::vector<int> off;
+  std::vector<double> d;
+  upwind(t.p, off, d);
+  // Z = dt L: (Z u)_i = -c sum_j d_j u_{i+j}; as first-column offset o = -j.
+  std::map<int, double> Z;
+  for (size_t j = 0; j < off.size(); ++j) Z[-off[j]] += -cfl * d[j];
+  // stability polynomial coefficients g_0 = 1, g_k = b^T A^{k-1} 1
+  double v[MAX_STAGES], nv[MAX_STAGES];
+  for (int i = 0; i < t.s; ++i) v[i] = 1.0;
+  std::vector<double> g(1, 1.0);
+  for (int k = 1; k <= t.s; ++k) {
+    double gk = 0.0;
+    for (int i = 0; i < t.s; ++i) gk += t.b[i] * v[i];
+    g.push_back(gk);
+    for (int i = 0; i < t.s; ++i) {
+      nv[i] = 0.0;
+      for (int j = 0; j < t.s; ++j) nv[i] += t.A[i][j] * v[j];
+    }
+    for (int i = 0; i < t.s; ++i) v[i] = nv[i];
+  }
+  std::map<int, double> phi, pw;  // pw = Z^k
+  pw[0] = 1.0;
+  phi[0] = g[0];
+  for (int k = 1; k <= t.s; ++k) {
+    std::map<int, double> nxt;
+    for (auto& a : pw)
+      for (auto& b : Z) nxt[a.first + b.first] += a.second * b.second;
+    pw.swap(nxt);
+    for (auto& a : pw) phi[a.first] += g[k] * a.second;
+  }
+  std::map<int, double> folded;
+  for (auto& a : phi) folded[((a.first % nx) + nx) % nx] += a.second;
+  double mx = 0.0;
+  for (auto& a : folded) mx = std::max(mx, std::fabs(a.second));
+  out.off.clear();
+  out.w.clear();
+  for (auto& a : folded)
+    if (std::fabs(a.second) > 1e-13 * mx) {
+      out.off.push_back(a.first);
+      out.w.push_back(a.second);
+    }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// DFTs with exactly reduced angles
+// ---------------------------------------------------------------------------
+static void roots_of_unity(int n, std::vector<cd>& w) {
+  // w[q] = exp(-2 pi i q / n)
+  w.resize(n);
+  for (int q = 0; q < n; ++q) {
+    double a = -2.0 * kPi * (double)q / (double)n;
+    w[q] = cd(std::cos(a), std::sin(a));
+  }
+}
+
+void dft(std::vector<cd>& a, bool inverse) {
+  const int n = (int)a.size();
+  std::vector<cd> w;
+  roots_of_unity(n, w);
+  if (n > 0 && (n & (n - 1)) == 0) {
+    // iterative radix-2
+    for (int i = 1, j = 0; i < n; ++i) {
+      int bit = n >> 1;
+      for (; j & bit; bit >>= 1) j ^= bit;
+      j ^= bit;
+      if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+      const int step = n / len;
+      for (int i = 0; i < n; i += len)
+        for (int k = 0; k < len / 2; ++k) {
+          cd tw = w[k * step];
+          if (inverse) tw = std::conj(tw);
+          cd u = a[i + k], v = a[i + k + len / 2] * tw;
+          a[i + k] = u + v;
+          a[i + k + len / 2] = u - v;
+        }
+    }
+  } else {
+    std::vector<cd> out(n);
+    for (int k = 0; k < n; ++k) {
+      cd s = 0.0;
+      for (int t = 0; t < n; ++t) {
+        cd tw = w[(int)(((long long)k * t) % n)];
+        s += a[t] * (inverse ? std::conj(tw) : tw);
+      }
+      out[k] = s;
+    }
+    a.swap(out);
+  }
+  if (inverse)
+    for (auto& x : a) x /= (double)n;
+}
+
+void taps_eigs(const Taps& t, int nx, std::vector<cd>& mu) {
+  std::vector<cd> w;
+  roots_of_unity(nx, w);
+  mu.assign(nx, cd(0.0));
+  for (size_t q = 0; q < t.off.size(); ++q) {
+    long long o = ((t.off[q] % nx) + nx) % nx;
+    for (int k = 0; k < nx; ++k) mu[k] += t.w[q] * w[(int)((k * o) % nx)];
+  }
+}
+
+static cd ipow(cd z, int m) {
+  cd r = 1.0;
+  while (m > 0) {
+    if (m & 1) r *= z;
+    z *= z;
+    m >>= 1;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (9): complex Householder QR least squares
+// ---------------------------------------------------------------------------
+double lsq_psi(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
+               std::vector<double>& wout) {
+  const int n = (int)lam.size();
+  const int v = (int)offs.size();
+  std::vector<cd> w;
+  roots_of_unity(n, w);
+  std::vector<cd> M((size_t)n * v), b(n);
+  for (int k = 0; k < n; ++k) {
+    double a = std::abs(lam[k]);
+    double sw = 1.0 / (1.0 - a + 1e-6);  // sqrt of w(|lambda|) = 1/(1-|l|+eps)^2
+    b[k] = sw * ipow(lam[k], m);
+    for (int t = 0; t < v; ++t) {
+      long long o = ((offs[t] % n) + n) % n;
+      M[(size_t)t * n + k] = sw * w[(int)((k * o) % n)];
+    }
+  }
+  for (int j = 0; j < v; ++j) {
+    cd* col = &M[(size_t)j * n];
+    double nrm2 = 0.0;
+    for (int i = j; i < n; ++i) nrm2 += std::norm(col[i]);
+    double nrm = std::sqrt(nrm2);
+    if (nrm == 0.0) continue;
+    cd x0 = col[j];
+    cd phase = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1.0);
+    cd alpha = -phase * nrm;
+    std::vector<cd> h(col + j, col + n);
+    h[0] -= alpha;
+    double hn2 = 0.0;
+    for (auto& x : h) hn2 += std::norm(x);
+    if (hn2 == 0.0) continue;
+    for (int k = j; k < v; ++k) {
+      cd* ck = &M[(size_t)k * n];
+      cd s = 0.0;
+      for (int i = j; i < n; ++i) s += std::conj(h[i - j]) * ck[i];
+      s *= 2.0 / hn2;
+      for (int i = j; i < n; ++i) ck[i] -= s * h[i - j];
+    }
+    cd s = 0.0;
+    for (int i = j; i < n; ++i) s += std::conj(h[i - j]) * b[i];
+    s *= 2.0 / hn2;
+    for (int i = j; i < n; ++i) b[i] -= s * h[i - j];
+  }
+  std::vector<cd> x(v);
+  for (int j = v - 1; j >= 0; --j) {
+    cd s = b[j];
+    for (int k = j + 1; k < v; ++k) s -= M[(size_t)k * n + j] * x[k];
+    x[j] = s / M[(size_t)j * n + j];
+  }
+  double mi = 0.0;
+  wout.resize(v);
+  for (int j = 0; j < v; ++j) {
+    wout[j] = x[j].real();
+    mi = std::max(mi, std::fabs(x[j].imag()));
+  }
+  return mi;
+}
+
+// ---------------------------------------------------------------------------
+// Sparsity patterns (Sec. 4.3 window rule, Sec. 4.6 thresholding)
+// ---------------------------------------------------------------------------
+static const double kEta[4][6] = {{0.1, 0.125, 0.25, 0.5, 0.5, 0.6},
+                                  {0.05, 0.1, 0.1, 0.2, 0.2, 0.2},
+                                  {0.005, 0.01, 0.02, 0.02, 0.02, 0.04},
+                                  {0.005, 0.01, 0.01, 0.01, 0.02, 0.02}};
+
+static double eta_table(int p, int m) {
+  if (p < 1 || p > 4) return -1.0;
+  int idx = -1;
+  for (int i = 0, mm = 2; i < 6; ++i, mm *= 2)
+    if (mm == m) idx = i;
+  return idx < 0 ? -1.0 : kEta[p - 1][idx];
+}
+
+static std::vector<int> threshold(const std::vector<double>& col, double eta) {
+  double mx = 0.0;
+  for (double c : col) mx = std::max(mx, std::fabs(c));
+  std::vector<int> o;
+  for (int i = 0; i < (int)col.size(); ++i)
+    if (std::fabs(col[i]) >= eta * mx) o.push_back(i);
+  return o;
+}
+
+static int cyclic_span(const std::vector<int>& offs, int n) {
+  std::vector<int> s(offs);
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  if (s.size() <= 1) return (int)s.size();
+  int gap = s.front() + n - s.back();
+  for (size_t i = 1; i < s.size(); ++i) gap = std::max(gap, s[i] - s[i - 1]);
+  return n - gap + 1;
+}
+
+// Smallest a whose window sum reaches the maximum up to a relative 1e-12.
+static std::vector<int> best_window(const std::vector<double>& col, int width) {
+  const int n = (int)col.size();
+  width = std::min(width, n);
+  std::vector<double> sums(n, 0.0);
+  double s = 0.0;
+  for (int i = 0; i < width; ++i) s += std::fabs(col[i]);
+  for (int a = 0; a < n; ++a) {
+    // recompute exactly every 256 starts to bound drift of the running sum
+    if (a % 256 == 0) {
+      s = 0.0;
+      for (int i = 0; i < width; ++i) s += std::fabs(col[(a + i) % n]);
+    }
+    sums[a] = s;
+    s += std::fabs(col[(a + width) % n]) - std::fabs(col[a]);
+  }
+  double mx = *std::max_element(sums.begin(), sums.end());
+  int start = 0;
+  for (int a = 0; a < n; ++a)
+    if (sums[a] >= mx * (1.0 - 1e-12)) {
+      start = a;
+      break;
+    }
+  std::vector<int> o(width);
+  for (int i = 0; i < width; ++i) o[i] = (start + i) % n;
+  return o;
+}
+
+int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
+                  const int* widths, double eta, std::vector<Taps>& out,
+                  double& max_imag) {
+  Tableau t;
+  if (!get_tableau(scheme, t)) return MGRIT_EINVAL;
+  if (nx < 2 || m < 2 || levels < 2 || !(cfl > 0.0)) return MGRIT_EINVAL;
+  if (rule == MGRIT_PSI_AUTO) rule = t.implicit ? MGRIT_PSI_ETA : MGRIT_PSI_WINDOW;
+  out.clear();
+  max_imag = 0.0;
+  if (rule == MGRIT_PSI_REDISC) {
+    if (t.implicit) return MGRIT_EINVAL;
+    double c = cfl;
+    for (int l = 1; l < levels; ++l) {
+      c *= m;
+      Taps tp;
+      erk_taps(t, c, nx, tp);
+      out.push_back(tp);
+    }
+    return MGRIT_OK;
+  }
+  if (rule != MGRIT_PSI_WINDOW && rule != MGRIT_PSI_ETA) return MGRIT_EINVAL;
+  std::vector<cd> lam(nx);
+  for (int k = 0; k < nx; ++k) lam[k] = step_symbol(t, cfl, 2.0 * kPi * k / nx);
+  int nnz_prev = 0;
+  if (!t.implicit) {
+    Taps f;
+    erk_taps(t, cfl, nx, f);
+    nnz_prev = (int)f.off.size();
+  }
+  for (int l = 1; l < levels; ++l) {
+    std::vector<cd> col(nx);
+    for (int k = 0; k < nx; ++k) col[k] = ipow(lam[k], m);
+    dft(col, true);
+    std::vector<double> rcol(nx);
+    for (int k = 0; k < nx; ++k) rcol[k] = col[k].real();
+    std::vector<int> offs;
+    if (rule == MGRIT_PSI_ETA) {
+      double e = eta > 0.0 ? eta : (t.implicit ? eta_table(t.p, m) : -1.0);
+      if (e <= 0.0) return MGRIT_EINVAL;
+      offs = threshold(rcol, e);
+    } else {
+      int wdt = widths ? widths[l - 1]
+                       : std::max(nnz_prev, cyclic_span(threshold(rcol, 0.02), nx));
+      if (wdt < 1) return MGRIT_EINVAL;
+      offs = best_window(rcol, wdt);
+    }
+    Taps tp;
+    tp.off = offs;
+    max_imag = std::max(max_imag, lsq_psi(lam, m, offs, tp.w));
+    taps_eigs(tp, nx, lam);
+    nnz_prev = (int)offs.size();
+    out.push_back(tp);
+  }
+  return max_imag > 1e-8 ? MGRIT_EIMAG : MGRIT_OK;
+}
+
+void tap_window(const Taps& t, int nx, int& omin, int& W, std::vector<double>& dense) {
+  std::map<int, double> f;
+  for (size_t q = 0; q < t.off.size(); ++q) f[((t.off[q] % nx) + nx) % nx] += t.w[q];
+  std::vector<int> s;
+  for (auto& a : f) s.push_back(a.first);
+  if (s.empty()) {
+    omin = 0;
+    W = 1;
+    dense.assign(1, 0.0);
+    return;
+  }
+  // the window starts right after the largest cyclic gap
+  int best_gap = s.front() + nx - s.back(), start = s.front();
+  for (size_t i = 1; i < s.size(); ++i)
+    if (s[i] - s[i - 1] > best_gap) {
+      best_gap = s[i] - s[i - 1];
+      start = s[i];
+    }
+  W = (s.size() == 1) ? 1 : nx - best_gap + 1;
+  omin = start;
+  dense.assign(W, 0.0);
+  for (auto& a : f) dense[((a.first - omin) % nx + nx) % nx] += a.second;
+}
+
+// ---------------------------------------------------------------------------
+// SDIRK stage matrix M = I - gamma dt L as cyclic recurrences
+// ---------------------------------------------------------------------------
+static std::vector<cd> poly_roots(const std::vector<double>& p) {
+  // p[q] = coefficient of s^q, degree D = p.size()-1; Durand-Kerner + Newton.
+  const int D = (int)p.size() - 1;
+  std::vector<cd> a(D + 1);
+  for (int q = 0; q <= D; ++q) a[q] = p[q] / p[D];
+  auto ev = [&](cd z) {
+    cd r = a[D];
+    for (int q = D - 1; q >= 0; --q) r = r * z + a[q];
+    return r;
+  };
+  auto dev = [&](cd z) {
+    cd r = (double)D * a[D];
+    for (int q = D - 1; q >= 1; --q) r = r * z + (double)q * a[q];
+    return r;
+  };
+  std::vector<cd> z(D);
+  cd seed(0.4, 0.9);
+  for (int i = 0; i < D; ++i) z[i] = std::pow(seed, i) * (1.0 + std::abs(a[0]));
+  for (int it = 0; it < 1000; ++it) {
+    double delta = 0.0;
+    for (int i = 0; i < D; ++i) {
+      cd den = 1.0;
+      for (int j = 0; j < D; ++j)
+        if (j != i) den *= (z[i] - z[j]);
+      cd dz = ev(z[i]) / den;
+      z[i] -= dz;
+      delta = std::max(delta, std::abs(dz));
+    }
+    if (delta < 1e-16) break;
+  }
+  for (int i = 0; i < D; ++i)
+    for (int it = 0; it < 3; ++it) {
+      cd d = dev(z[i]);
+      if (std::abs(d) > 0) z[i] -= ev(z[i]) / d;
+    }
+  return z;
+}
+
+static void mat2_mul(const double* a, const double* b, double* c) {
+  double r[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
+                 a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
+  for (int i = 0; i < 4; ++i) c[i] = r[i];
+}
+
+static void mat2_pow(const double* a, long long e, double* out) {
+  double r[4] = {1, 0, 0, 1}, b[4] = {a[0], a[1], a[2], a[3]};
+  while (e > 0) {
+    if (e & 1) mat2_mul(r, b, r);
+    mat2_mul(b, b, b);
+    e >>= 1;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = r[i];
+}
+
+bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
+                 std::string& err) {
+  out = SdirkDev();
+  if (!t.implicit) {
+    err = "not an SDIRK scheme";
+    return false;
+  }
+  const double g = t.A[0][0];
+  for (int i = 1; i < t.s; ++i)
+    if (std::fabs(t.A[i][i] - g) > 1e-15) {
+      err = "tableau is not singly diagonal";
+      return false;
+    }
+  std::vector<int> off;
+  std::vector<double> d;
+  upwind(t.p, off, d);
+  // (M u)_i = sum_j coef_j u_{i+j};  M = I + gamma c D.
+  std::map<int, double> coef;
+  for (size_t j = 0; j < off.size(); ++j) coef[off[j]] += g * cfl * d[j];
+  coef[0] += 1.0;
+  const int jmin = coef.begin()->first, jmax = coef.rbegin()->first;
+  const int D = jmax - jmin;
+  // S^{jmax} M = P(S), P(s) = sum_j coef_j s^{jmax - j}, S u_i = u_{i-1}
+  std::vector<double> p(D + 1, 0.0);
+  for (auto& c : coef) p[jmax - c.first] = c.second;
+  std::vector<cd> r = poly_roots(p);
+  std::vector<cd> outside, inside;
+  for (auto& z : r) {
+    if (std::fabs(std::abs(z) - 1.0) < 1e-10) {
+      err = "stage matrix has a root on the unit circle";
+      return false;
+    }
+    (std::abs(z) > 1.0 ? outside : inside).push_back(z);
+  }
+  if ((int)inside.size() != jmax) {
+    err = "unexpected root split of the stage matrix";
+    return false;
+  }
+  cd Kc = coef.begin()->second;
+  for (auto& z : outside) Kc *= -z;
+  // group roots into factors of order <= 2 with real coefficients
+  auto make_factors = [&](std::vector<cd> roots, int dir) {
+    std::vector<RecDev> fs;
+    std::vector<bool> used(roots.size(), false);
+    std::vector<cd> reals;
+    for (size_t i = 0; i < roots.size(); ++i) {
+      if (used[i]) continue;
+      if (std::fabs(roots[i].imag()) > 1e-12 * std::abs(roots[i])) {
+        size_t best = i;
+        double bd = 1e300;
+        for (size_t j = 0; j < roots.size(); ++j)
+          if (j != i && !used[j]) {
+            double dd = std::abs(roots[j] - std::conj(roots[i]));
+            if (dd < bd) { bd = dd; best = j; }
+          }
+        used[i] = used[best] = true;
+        RecDev f = {};
+        f.dir = dir;
+        cd q1 = dir > 0 ? 1.0 / roots[i] : roots[i];
+        cd q2 = dir > 0 ? 1.0 / roots[best] : roots[best];
+        f.a1 = (q1 + q2).real();
+        f.a2 = -(q1 * q2).real();
+        fs.push_back(f);
+      } else {
+        used[i] = true;
+        reals.push_back(roots[i]);
+      }
+    }
+    for (size_t i = 0; i < reals.size(); i += 2) {
+      RecDev f = {};
+      f.dir = dir;
+      double q1 = dir > 0 ? 1.0 / reals[i].real() : reals[i].real();
+      if (i + 1 < reals.size()) {
+        double q2 = dir > 0 ? 1.0 / reals[i + 1].real() : reals[i + 1].real();
+        f.a1 = q1 + q2;
+        f.a2 = -q1 * q2;
+      } else {
+        f.a1 = q1;
+        f.a2 = 0.0;
+      }
+      fs.push_back(f);
+    }
+    return fs;
+  };
+  std::vector<RecDev> fs = make_factors(outside, +1);
+  std::vector<RecDev> fb = make_factors(inside, -1);
+  fs.insert(fs.end(), fb.begin(), fb.end());
+  if ((int)fs.size() > MAX_FACTORS) {
+    err = "too many recurrence factors";
+    return false;
+  }
+  // check: K * prod_f (1 - a1 X - a2 X^2) (X = S or S^{-1}) reproduces M
+  {
+    std::map<int, double> prod;
+    prod[0] = Kc.real();
+    for (auto& f : fs) {
+      std::map<int, double> nxt;
+      // factor as Laurent polynomial in S: dir +1 -> powers 0, 1, 2 of S
+      // (first-column offsets 0, 1, 2); dir -1 -> offsets 0, -1, -2
+      int s1 = f.dir > 0 ? 1 : -1;
+      for (auto& a : prod) {
+        nxt[a.first] += a.second;
+        nxt[a.first + s1] += -f.a1 * a.second;
+        nxt[a.first + 2 * s1] += -f.a2 * a.second;
+      }
+      prod.swap(nxt);
+    }
+    double mx = 0.0;
+    for (auto& c : coef) mx = std::max(mx, std::fabs(c.second));
+    std::map<int, double> want;  // first-column offsets of M: o = -j
+    for (auto& c : coef) want[-c.first] = c.second;
+    for (auto& a : prod) {
+      double w = want.count(a.first) ? want[a.first] : 0.0;
+      if (std::fabs(a.second - w) > 1e-12 * mx) {
+        err = "stage-matrix factorization check failed";
+        return false;
+      }
+    }
+  }
+  out.s = t.s;
+  out.nf = (int)fs.size();
+  out.K = K;
+  out.NL = NL;
+  for (int i = 0; i < t.s; ++i) {
+    for (int j = 0; j < t.s; ++j) out.A[i][j] = t.A[i][j];
+    out.b[i] = t.b[i];
+  }
+  out.inv_gamma = 1.0 / g;
+  out.scale = 1.0 / Kc.real();
+  for (int q = 0; q < out.nf; ++q) {
+    RecDev f = fs[q];
+    double C[4] = {f.a1, f.a2, 1.0, 0.0};
+    double H[4];
+    mat2_pow(C, K, H);
+    for (int dd = 0; dd < 11; ++dd) mat2_pow(H, 1LL << dd, f.Hp[dd]);
+    double HN[4];
+    mat2_pow(H, NL, HN);
+    double a = 1.0 - HN[0], b = -HN[1], c = -HN[2], e = 1.0 - HN[3];
+    double det = a * e - b * c;
+    if (!(std::fabs(det) > 1e-300)) {
+      err = "singular cyclic closure";
+      return false;
+    }
+    f.Cinv[0] = e / det;
+    f.Cinv[1] = -b / det;
+    f.Cinv[2] = -c / det;
+    f.Cinv[3] = a / det;
+    out.f[q] = f;
+  }
+  return true;
+}
+
+}  // namespace mgr

@@ -1,0 +1,76 @@
+// Host-side setup of libmgrit: discretizations, stencils, Fourier symbols,
+// the least-squares coarse operators and the SDIRK stage factorization.
+// Pure C++ (no HIP); everything here runs once per plan, off the hot path.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mgr {
+
+using cd = std::complex<double>;
+
+struct Tableau {
+  int s = 0;          // stages
+  int p = 0;          // order (= index of the upwind formula Up)
+  bool implicit = false;
+  double A[MAX_STAGES][MAX_STAGES] = {};
+  double b[MAX_STAGES] = {};
+};
+
+// Appendix A, Tables 7 (ERK1-5) and 8 (SDIRK1-4); scheme ids of mgrit.h.
+bool get_tableau(int scheme, Tableau& t);
+
+// Sec. 2.1, formulas U1-U5: v'_i ~ (1/dx) sum_j d[j] v_{i + off[j]}.
+void upwind(int p, std::vector<int>& off, std::vector<double>& d);
+
+// Stability function R(z) = 1 + z b^T (I - z A)^{-1} 1 (Lemma 1).
+cd stability(const Tableau& t, cd z);
+
+// Eigenvalue of Phi on Fourier mode theta: R(dt * l(theta)) with
+// dt l(theta) = -c sum_j d_j exp(i j theta).
+cd step_symbol(const Tableau& t, double cfl, double theta);
+
+// max_theta |R| over a fine grid of [0, pi].
+double max_amplification(const Tableau& t, double cfl);
+
+struct Taps {
+  std::vector<int> off;     // offsets in [0, nx)
+  std::vector<double> w;
+};
+
+// Phi of an explicit scheme as a stencil: R(Z) with Z = dt L expanded as a
+// polynomial of the shift operator (Corollary 1), offsets folded mod nx.
+bool erk_taps(const Tableau& t, double cfl, int nx, Taps& out);
+
+// In-place DFT (forward: exp(-2 pi i k n / N); inverse includes 1/N).
+void dft(std::vector<cd>& a, bool inverse);
+
+// Eigenvalues of a stencil: mu_k = sum_t w_t exp(-2 pi i k o_t / nx).
+void taps_eigs(const Taps& t, int nx, std::vector<cd>& mu);
+
+// Eq. (9): weighted least squares for the pattern `offs`; returns the real
+// part of the solution in w and the largest imaginary part.
+double lsq_psi(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
+               std::vector<double>& w);
+
+// The coarse hierarchy of mgrit_psi_optimize (see mgrit.h).
+int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
+                  const int* widths, double eta, std::vector<Taps>& out,
+                  double& max_imag);
+
+// Minimal cyclic window [omin, omin+W) of [0, nx) holding every offset;
+// `dense` receives the W weights (zeros off-pattern).  Offsets are merged
+// mod nx first.
+void tap_window(const Taps& t, int nx, int& omin, int& W,
+                std::vector<double>& dense);
+
+// SDIRK: factor M = I - gamma dt L into cyclic recurrences (see common.h)
+// and fill the stage data; scan constants for chunk K and NL lanes.
+bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
+                 std::string& err);
+
+}  // namespace mgr

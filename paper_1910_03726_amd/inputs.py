@@ -42,6 +42,21 @@ def random_iterate(npoints, nx, seed):
     return np.random.default_rng(seed).random((npoints, nx))
 
 
+def splitmix_iterate(npoints, nx, seed):
+    """U[0,1) values of the splitmix64 stream (Steele, Lea & Flood, 2014):
+    value i = mix(seed + (i+1) * 0x9E3779B97F4A7C15) >> 11, times 2^-53.
+    The same counter-based stream fills the initial iterate on the device
+    when none is passed in."""
+    with np.errstate(over="ignore"):
+        i = np.arange(npoints * nx, dtype=np.uint64)
+        z = np.uint64(seed) + (i + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return ((z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+            ).reshape(npoints, nx)
+
+
 # Courant numbers c = alpha dt/dx of the workloads.  ERK: 85% of the Table 1
 # CFL limit (1, 1/2, 1.62589, 1.04449, 1.96583); SDIRK: c = 4 (Sec. 2.1).
 CFL_LIMIT_TABLE1 = {1: 1.0, 2: 0.5, 3: 1.62589, 4: 1.04449, 5: 1.96583}

@@ -1,0 +1,284 @@
+"""Python binding of libmgrit (include/mgrit.h): argument marshalling only.
+
+Every computation runs in libmgrit.so: the host setup of the coarse
+operators in its C++ code, every step of a solve in its gfx950 kernels.
+PyTorch supplies device memory (float64 CUDA tensors, passed by pointer)
+and the HIP stream.  There is no fallback: if the library is missing,
+``lib()`` raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgrit.so")
+_lib = None
+
+SCHEMES = {"ERK1": 1, "ERK2": 2, "ERK3": 3, "ERK4": 4, "ERK5": 5,
+           "SDIRK1": 11, "SDIRK2": 12, "SDIRK3": 13, "SDIRK4": 14}
+CYCLES = {"V": 0, "F": 1}
+RELAX = {"FCF": 0, "F": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+PSI_RULES = {"auto": 0, "window": 1, "eta": 2, "redisc": 3}
+OUT = {"none": 0, "final": 1, "cpoints": 2, "all": 3}
+
+OK, EINVAL, EUNSTABLE, ENOMEM, EHIP, ENOTCONV, EDIVERGED, EIMAG, ENODEV, \
+    ECAPACITY, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
+PROF_CLASSES = ("relax_fine", "relax_coarse", "coarsest", "norm", "other")
+
+
+class MgritError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().mgrit_strerror(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+class Taps(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int), ("offset", ctypes.POINTER(ctypes.c_int)),
+                ("weight", ctypes.POINTER(ctypes.c_double))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("fine_passes_fp64", ctypes.c_int), ("fine_passes_fp32", ctypes.c_int),
+                ("final_residual", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_longlong * 5),
+                ("fine_dof_steps", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "mgrit_version": (_I, []),
+    "mgrit_strerror": (ctypes.c_char_p, [_I]),
+    "mgrit_max_amplification": (_I, [_I, _D, ctypes.POINTER(_D)]),
+    "mgrit_phi_taps": (_I, [_I, _D, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_D),
+                            ctypes.POINTER(_I)]),
+    "mgrit_psi_optimize": (_I, [_I, _D, _I, _I, _I, _I, ctypes.POINTER(_I), _D,
+                                ctypes.POINTER(Taps), ctypes.POINTER(_D)]),
+    "mgrit_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _I, _I, _I,
+                               ctypes.POINTER(Taps), _I, _I, _I, _P]),
+    "mgrit_solve": (_I, [_P, _P, _P, _D, _I, _P, _I, ctypes.POINTER(_D),
+                         ctypes.POINTER(_I)]),
+    "phi_apply_batch": (_I, [_P, _P, _P, _I, _I]),
+    "mgrit_plan_bytes": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "mgrit_plan_set_seed": (_I, [_P, ctypes.c_ulonglong]),
+    "mgrit_get_stats": (_I, [_P, ctypes.POINTER(Stats)]),
+    "mgrit_set_profiling": (_I, [_P, _I]),
+    "mgrit_get_profile": (_I, [_P, ctypes.POINTER(Profile)]),
+    "mgrit_operator_complexity": (_I, [_P, ctypes.POINTER(_D)]),
+    "mgrit_plan_describe": (ctypes.c_char_p, [_P]),
+    "mgrit_destroy": (None, [_P]),
+}
+
+
+def lib():
+    """The loaded libmgrit.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1910_03726_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise MgritError(rc, what)
+
+
+def _scheme(s):
+    return SCHEMES[s] if isinstance(s, str) else int(s)
+
+
+def max_amplification(scheme, cfl):
+    v = _D()
+    _check(lib().mgrit_max_amplification(_scheme(scheme), cfl, ctypes.byref(v)),
+           "mgrit_max_amplification")
+    return v.value
+
+
+def phi_taps(scheme, cfl, nx):
+    """Collapsed ERK stepper (offsets in [0, nx), weights)."""
+    cap = 256
+    off = (_I * cap)()
+    w = (_D * cap)()
+    n = _I()
+    _check(lib().mgrit_phi_taps(_scheme(scheme), cfl, nx, cap, off, w, ctypes.byref(n)),
+           "mgrit_phi_taps")
+    return np.array(off[:n.value]), np.array(w[:n.value])
+
+
+def psi_optimize(scheme, cfl, nx, m, levels, rule="auto", widths=None, eta=0.0,
+                 capacity=None, allow_imag=False):
+    """Coarse operators Psi_2..Psi_L: list of (offsets, weights), max_imag."""
+    cap = capacity or max(64, nx)
+    bufs = []
+    arr = (Taps * (levels - 1))()
+    for i in range(levels - 1):
+        o = (_I * cap)()
+        w = (_D * cap)()
+        bufs.append((o, w))
+        arr[i].nnz = cap
+        arr[i].offset = o
+        arr[i].weight = w
+    wd = None
+    if widths is not None:
+        wd = (_I * len(widths))(*[int(x) for x in widths])
+    mi = _D()
+    rc = lib().mgrit_psi_optimize(_scheme(scheme), cfl, nx, m, levels, PSI_RULES[rule],
+                                  wd, eta, arr, ctypes.byref(mi))
+    if not (rc == OK or (rc == EIMAG and allow_imag)):
+        raise MgritError(rc, "mgrit_psi_optimize")
+    out = []
+    for i in range(levels - 1):
+        n = arr[i].nnz
+        out.append((np.array(bufs[i][0][:n]), np.array(bufs[i][1][:n])))
+    return out, mi.value
+
+
+def _ptr(t, name, numel=None):
+    import torch
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} values, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class SolveResult:
+    def __init__(self, status, iters, hist, out, stats):
+        self.status = status
+        self.iters = iters
+        self.hist = hist
+        self.out = out
+        self.stats = stats
+
+    @property
+    def converged(self):
+        return self.status == OK
+
+
+class Plan:
+    """An MGRIT plan on the current HIP device (see mgrit_plan_create)."""
+
+    def __init__(self, nx, nt, cfl, scheme, m, levels, psi, alpha=1.0, cycle="V",
+                 relax="FCF", precision="fp64", stream=None):
+        import torch
+        self.nx, self.nt, self.m, self.levels = int(nx), int(nt), int(m), int(levels)
+        self.scheme = scheme
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        arr = (Taps * max(1, levels - 1))()
+        keep = []
+        for i, (o, w) in enumerate(psi):
+            oa = (_I * len(o))(*[int(x) for x in o])
+            wa = (_D * len(w))(*[float(x) for x in w])
+            keep.append((oa, wa))
+            arr[i].nnz = len(o)
+            arr[i].offset = oa
+            arr[i].weight = wa
+        h = _P()
+        rc = lib().mgrit_plan_create(ctypes.byref(h), self.nx, self.nt, alpha, cfl,
+                                     _scheme(scheme), self.m, self.levels, arr,
+                                     CYCLES[cycle], RELAX[relax], PRECISION[precision],
+                                     ctypes.c_void_p(stream))
+        _check(rc, "mgrit_plan_create")
+        self._h = h
+
+    @property
+    def nc(self):
+        return self.nt // self.m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgrit_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def solve(self, u0, uinit=None, tol=1e-10, maxit=100, out="final", u_out=None):
+        import torch
+        nx, nc = self.nx, self.nc
+        rows = {"none": 0, "final": 1, "cpoints": nc + 1, "all": self.nt + 1}[out]
+        if out != "none" and u_out is None:
+            u_out = torch.empty((rows, nx), dtype=torch.float64, device=u0.device)
+        hist = (_D * (maxit + 1))()
+        it = _I()
+        rc = lib().mgrit_solve(self._h, _ptr(u0, "u0", nx),
+                               _ptr(uinit, "uinit", (nc + 1) * nx), tol, maxit,
+                               _ptr(u_out, "u_out", rows * nx) if out != "none" else None,
+                               OUT[out], hist, ctypes.byref(it))
+        if rc not in (OK, ENOTCONV, EDIVERGED):
+            raise MgritError(rc, "mgrit_solve")
+        st = self.stats()
+        nh = (st.outer_iterations if self.precision == "fp32" else it.value) + 1
+        return SolveResult(rc, it.value, list(hist[:nh]), u_out, st)
+
+    def phi_apply_batch(self, inp, out, ksteps):
+        b = inp.numel() // self.nx
+        _ptr(inp, "in", b * self.nx)
+        _ptr(out, "out", b * self.nx)
+        _check(lib().phi_apply_batch(self._h, ctypes.c_void_p(inp.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), b, ksteps),
+               "phi_apply_batch")
+
+    def bytes(self):
+        v = ctypes.c_size_t()
+        _check(lib().mgrit_plan_bytes(self._h, ctypes.byref(v)), "mgrit_plan_bytes")
+        return v.value
+
+    def set_seed(self, seed):
+        _check(lib().mgrit_plan_set_seed(self._h, seed), "mgrit_plan_set_seed")
+
+    def stats(self):
+        s = Stats()
+        _check(lib().mgrit_get_stats(self._h, ctypes.byref(s)), "mgrit_get_stats")
+        return s
+
+    def set_profiling(self, on):
+        _check(lib().mgrit_set_profiling(self._h, 1 if on else 0), "mgrit_set_profiling")
+
+    def profile(self):
+        p = Profile()
+        _check(lib().mgrit_get_profile(self._h, ctypes.byref(p)), "mgrit_get_profile")
+        return {"ms": dict(zip(PROF_CLASSES, list(p.ms))),
+                "launches": dict(zip(PROF_CLASSES, list(p.launches))),
+                "fine_dof_steps": p.fine_dof_steps}
+
+    def operator_complexity(self):
+        v = _D()
+        _check(lib().mgrit_operator_complexity(self._h, ctypes.byref(v)),
+               "mgrit_operator_complexity")
+        return v.value
+
+    def describe(self):
+        return lib().mgrit_plan_describe(self._h).decode()

@@ -1,0 +1,233 @@
+"""GPU parity of libmgrit (through its C-ABI) against the CPU oracle.
+
+Every expected value comes from the oracle on the same seeded inputs.
+Tolerances (FP64): one fine step is rounding-exact up to the summation
+order of the collapsed stencil / recurrence factorization, so k steps agree
+to ~k*1e-16 relative; MGRIT solves run to tol <= 1e-13 so that the
+converged iterate agrees with sequential stepping to 1e-12 relative
+(error ~ |A^-1| |r|).  FP32 relaxation: 1e-5 per short propagation; the
+refinement form is held to its FP64 tolerance.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import coarse, mgrit as omg, rk
+from paper_1910_03726_amd import inputs, mgrit as M
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _oracle_hierarchy(d, m, levels, widths=None):
+    H = coarse.build_hierarchy(d, m, levels, widths=widths)
+    return [(h["offsets"], h["weights"]) for h in H]
+
+
+def _oracle_mgrit(d, psi, m, nt, cycle="V", relax="FCF"):
+    ops = [d.step] + [omg.taps_op(o, w) for o, w in psi]
+    return omg.MGRIT(ops, m, nt, cycle=cycle, relax=relax)
+
+
+IDENT = [(np.array([0]), np.array([1.0]))]
+
+
+# ---------------------------------------------------------------------------
+# one fine step: phi_apply_batch
+# ---------------------------------------------------------------------------
+PHI_CASES = [(s, nx) for s in ("ERK1", "ERK2", "ERK3", "ERK4", "ERK5")
+             for nx in (64, 256, 4096, 100, 200)] + \
+            [(s, nx) for s in ("SDIRK1", "SDIRK2", "SDIRK3", "SDIRK4")
+             for nx in (64, 256, 2048, 192)]
+
+
+@pytest.mark.parametrize("scheme,nx", PHI_CASES)
+def test_phi_apply_batch_fp64(scheme, nx):
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    with M.Plan(nx, 2, c, scheme, 2, 2, IDENT) as P:
+        rng = np.random.default_rng(7)
+        U = rng.standard_normal((5, nx))
+        out = torch.empty((5, nx), dtype=torch.float64, device=DEV)
+        for k in (1, 7):
+            P.phi_apply_batch(_t(U), out, k)
+            torch.cuda.synchronize()
+            assert _rel(_n(out), d.propagate(U, k)) < 2e-14 * k, P.describe()
+
+
+@pytest.mark.parametrize("scheme,nx", [("ERK3", 256), ("ERK5", 4096), ("ERK1", 100),
+                                       ("SDIRK3", 2048), ("SDIRK4", 256)])
+def test_phi_apply_batch_fp32(scheme, nx):
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    with M.Plan(nx, 2, c, scheme, 2, 2, IDENT, precision="fp32") as P:
+        U = np.random.default_rng(8).standard_normal((3, nx))
+        out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
+        P.phi_apply_batch(_t(U), out, 5)
+        torch.cuda.synchronize()
+        assert _rel(_n(out), d.propagate(U, 5)) < 2e-5
+
+
+def test_phi_apply_long_sequential():
+    # GPU sequential time-stepping (batch 1, k = n_t) against the oracle:
+    # random-walk rounding keeps the relative error far below 1e-12.
+    s, nx, nt = "ERK3", 1024, 4096
+    c = rk.paper_cfl(s)
+    d = rk.Discretization(s, nx, c)
+    u0 = inputs.fourier_u0(nx, 8, 0, decay=2.0)
+    with M.Plan(nx, 2, c, s, 2, 2, IDENT) as P:
+        out = torch.empty((1, nx), dtype=torch.float64, device=DEV)
+        P.phi_apply_batch(_t(u0[None]), out, nt)
+        torch.cuda.synchronize()
+    assert _rel(_n(out)[0], d.propagate(u0, nt)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# MGRIT solves against the oracle MGRIT (same Psi, same initial iterate)
+# ---------------------------------------------------------------------------
+def _compare(scheme, nx, nt, m, levels, cycle="V", relax="FCF", widths=None,
+             psi=None, tol=1e-10, maxit=60, u0=None, seed=1):
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    psi = _oracle_hierarchy(d, m, levels, widths) if psi is None else psi
+    u0 = inputs.fourier_u0(nx, 8, 0) if u0 is None else u0
+    nc = nt // m
+    uinit = inputs.random_iterate(nc + 1, nx, seed)
+    R = _oracle_mgrit(d, psi, m, nt, cycle, relax).solve(u0, uinit, tol, maxit,
+                                                          omg.norm_scale(d))
+    with M.Plan(nx, nt, c, scheme, m, levels, psi, cycle=cycle, relax=relax) as P:
+        g = P.solve(_t(u0), _t(uinit), tol=tol, maxit=maxit, out="cpoints")
+    return d, R, g, u0
+
+
+def _check_hist(g, R):
+    assert g.iters == R.iters
+    h0 = R.hist[0]
+    for a, b in zip(g.hist, R.hist):
+        assert abs(a - b) <= 1e-10 * h0 + 1e-6 * b, (g.hist, R.hist)
+
+
+@pytest.mark.parametrize("scheme,nx,nt,m,levels,cycle,widths", [
+    ("ERK1", 64, 256, 4, 2, "V", [3]),        # the 64 x 256 ERK1 workload
+    ("ERK3", 256, 1024, 8, 2, "V", None),
+    ("ERK5", 256, 1024, 8, 3, "V", None),
+    ("ERK3", 128, 2048, 4, 4, "V", None),
+    ("ERK3", 128, 2048, 4, 4, "F", None),
+    ("ERK1", 256, 1024, 4, 4, "V", [3, 6, 11]),
+    ("SDIRK3", 256, 256, 16, 2, "V", None),
+    ("SDIRK1", 128, 256, 4, 2, "V", None),
+    ("SDIRK2", 128, 256, 8, 2, "V", None),
+    ("SDIRK4", 128, 256, 8, 2, "V", None),
+    ("ERK3", 100, 400, 4, 3, "V", None),       # ragged n_x: generic kernel
+    ("ERK2", 192, 768, 4, 3, "F", None),
+])
+def test_mgrit_counts_and_history(scheme, nx, nt, m, levels, cycle, widths):
+    d, R, g, _ = _compare(scheme, nx, nt, m, levels, cycle=cycle, widths=widths)
+    assert R.status == "converged" and g.converged
+    _check_hist(g, R)
+    assert _rel(_n(g.out), R.cpoints) < 1e-9
+
+
+@pytest.mark.parametrize("scheme,nx,nt,m,levels,cycle", [
+    ("ERK3", 256, 1024, 8, 2, "V"), ("ERK5", 128, 1024, 4, 4, "F"),
+    ("SDIRK3", 256, 512, 16, 2, "V"), ("ERK1", 64, 256, 4, 3, "V")])
+def test_mgrit_solution_matches_sequential_stepping(scheme, nx, nt, m, levels, cycle):
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    psi = _oracle_hierarchy(d, m, levels)
+    u0 = inputs.fourier_u0(nx, 8, 0)
+    seq = d.time_stepping(u0, nt)
+    with M.Plan(nx, nt, c, scheme, m, levels, psi, cycle=cycle) as P:
+        g = P.solve(_t(u0), None, tol=1e-14, maxit=80, out="all")
+    assert g.converged
+    assert _rel(_n(g.out), seq) < 1e-12
+
+
+def test_parareal_f_relaxation_counts():
+    _, R, g, _ = _compare("ERK3", 128, 512, 4, 2, relax="F")
+    assert R.status == "converged"
+    _check_hist(g, R)
+
+
+def test_exactness_with_rediscretized_psi():
+    # Rediscretized Psi diverges (coarse CFL 3.4); FCF is exact after
+    # n_t/(2m) = 32 iterations: the residual is exactly zero on the GPU too.
+    w = inputs.WORKLOADS["erk1_u1_nx64_nt256_m4_2level"]
+    psi, _ = M.psi_optimize("ERK1", w["cfl"], 64, 4, 2, rule="redisc")
+    u0 = inputs.workload_u0(w)
+    uinit = inputs.random_iterate(65, 64, w["init_seed"])
+    with M.Plan(64, 256, w["cfl"], "ERK1", 4, 2, psi) as P:
+        g = P.solve(_t(u0), _t(uinit), tol=0.0, maxit=40)
+    assert g.iters == 32 and g.hist[-1] == 0.0 and g.hist[-2] > 0.0
+    assert max(g.hist) > 1e30
+
+
+def test_ideal_psi_one_iteration_generic_kernel():
+    # Psi = Phi^m with all n_x taps (window > 64: the generic LDS kernel).
+    s, nx, nt, m = "ERK3", 128, 512, 4
+    c = rk.paper_cfl(s)
+    d = rk.Discretization(s, nx, c)
+    col, _ = coarse.phi_m_first_column(d.eigenvalues(), m)
+    with M.Plan(nx, nt, c, s, m, 2, [(np.arange(nx), col)]) as P:
+        assert "generic" in P.describe()
+        g = P.solve(_t(inputs.fourier_u0(nx, 8, 0)), None, tol=1e-12, maxit=5)
+    assert g.iters == 1
+
+
+def test_seeded_initial_iterate_is_splitmix():
+    s, nx, nt, m = "ERK3", 128, 512, 8
+    c = rk.paper_cfl(s)
+    d = rk.Discretization(s, nx, c)
+    psi = _oracle_hierarchy(d, m, 2)
+    u0 = inputs.fourier_u0(nx, 8, 0)
+    with M.Plan(nx, nt, c, s, m, 2, psi) as P:
+        P.set_seed(12345)
+        a = P.solve(_t(u0), None, tol=1e-10)
+        b = P.solve(_t(u0), _t(inputs.splitmix_iterate(nt // m + 1, nx, 12345)), tol=1e-10)
+    assert a.hist == b.hist
+
+
+def test_fp32_relaxation_refinement():
+    # FP32 relaxation inside FP64 refinement reaches the FP64 tolerance and
+    # the FP64 solution.
+    s, nx, nt, m, L = "ERK5", 256, 2048, 8, 3
+    c = rk.paper_cfl(s)
+    d = rk.Discretization(s, nx, c)
+    psi = _oracle_hierarchy(d, m, L)
+    u0 = inputs.fourier_u0(nx, 16, 0)
+    seq = d.time_stepping(u0, nt, every=m)
+    with M.Plan(nx, nt, c, s, m, L, psi, precision="fp32") as P:
+        g = P.solve(_t(u0), None, tol=1e-10, maxit=10, out="cpoints")
+        st = P.stats()
+    assert g.converged and g.hist[-1] <= 1e-10
+    assert st.fine_passes_fp32 > 0 and st.outer_iterations >= 1
+    assert _rel(_n(g.out), seq) < 1e-8
+
+
+def test_errors():
+    with pytest.raises(M.MgritError) as e:
+        M.Plan(64, 256, 1.2, "ERK1", 4, 2, IDENT)
+    assert e.value.code == M.EUNSTABLE
+    with pytest.raises(M.MgritError) as e:
+        M.Plan(64, 250, 0.85, "ERK1", 4, 2, IDENT)
+    assert e.value.code == M.EINVAL
+    with pytest.raises(M.MgritError) as e:
+        M.Plan(100, 256, 4.0, "SDIRK3", 4, 2, IDENT)
+    assert e.value.code == M.EINVAL
+    with M.Plan(64, 256, 0.85, "ERK1", 4, 2, [(np.array([4]), np.array([1.0]))]) as P:
+        g = P.solve(_t(np.ones(64)), None, tol=1e-30, maxit=2)
+    assert g.status == M.ENOTCONV and g.iters == 2
