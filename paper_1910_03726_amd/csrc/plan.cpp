@@ -23,30 +23,51 @@ namespace mgr {
 // ---------------------------------------------------------------------------
 // kernel selection
 // ---------------------------------------------------------------------------
-static bool pick_stencil_shape(int nx, int Wb, bool seq, int& K, int& NL) {
-  // lanes own K contiguous points, NL = nx/K lanes, a multiple of 64 and at
-  // most 256 (one workgroup).  Interval relaxation prefers K = 16 (enough
-  // independent FMAs per lane, halo amortized); the single-workgroup
-  // sequential sweep prefers NL = 256 (one wavefront per SIMD of the CU).
-  int bestK = -1, bestNL = 0;
-  double best = 1e30;
+// LDS bytes of k_stencil for n_x, chunk K, NL lanes, compiled width Wb.
+static size_t stencil_lds(int nx, int K, int NL, int Wb, size_t el) {
+  const int H = std::min(Wb - 1, K);
+  const size_t stage = sizeof(double) * (size_t)(nx + nx / K);
+  return stage + ((Wb - 1 <= K) ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el : 0);
+}
+
+// Largest chunk K whose k_stencil<double,K,Wb,io> instantiation compiles
+// without register spills on gfx950 (from the compiler's resource usage
+// report: long chunks plus a wide window or a prefetched right-hand side
+// row exceed 256 VGPRs).
+static int max_spill_free_k(int Wb, bool io) {
+  if (!io) return Wb <= 32 ? 32 : 16;
+  if (Wb <= 24) return 16;
+  return 8;
+}
+
+static bool pick_stencil_shape(int nx, int Wb, bool seq, bool io, int& K, int& NL) {
+  // Lanes own K contiguous points, NL = nx/K lanes (a multiple of 64, at
+  // most 512).  Take the longest spill-free chunk (more independent FMAs per
+  // lane, halo amortized); the single-workgroup sequential sweep takes the
+  // most lanes (up to 512, two wavefronts per SIMD) within that bound.  If
+  // no spill-free shape has <= 512 lanes, take the shortest chunk that has.
+  // Every candidate must fit the CU's 160 KB of LDS.
+  const int kmax = max_spill_free_k(Wb, io);
+  int bestK = -1, fallbackK = -1;
   for (int i = 0; i < kNumK; ++i) {
     const int k = kKs[i];
     if (nx % k) continue;
     const int nl = nx / k;
-    if (nl % 64 || nl > 256 || nl < 64) continue;
+    if (nl % 64 || nl > 512 || nl < 64) continue;
     if (Wb - 1 > nx) continue;
-    double score = seq ? std::fabs(std::log2((double)nl) - 8.0)
-                       : std::fabs(std::log2((double)k) - 4.0);
-    if (score < best) {
-      best = score;
-      bestK = k;
-      bestNL = nl;
+    if (stencil_lds(nx, k, nl, Wb, sizeof(double)) > 160 * 1024) continue;
+    if (fallbackK < 0) fallbackK = k;  // kKs ascends: the shortest valid chunk
+    if (k > kmax) continue;
+    if (seq) {
+      if (bestK < 0) bestK = k;        // most lanes
+    } else {
+      bestK = k;                       // longest chunk
     }
   }
+  if (bestK < 0) bestK = fallbackK;
   if (bestK < 0) return false;
   K = bestK;
-  NL = bestNL;
+  NL = nx / K;
   return true;
 }
 
@@ -56,7 +77,7 @@ static int pick_width(int W) {
   return -1;
 }
 
-int OpDesc::init_stencil(const Taps& t, int nx, bool seq, std::string& err) {
+int OpDesc::init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& err) {
   const KernelTable& kt = kernel_table();
   nnz = (int)t.off.size();
   std::vector<double> dense;
@@ -65,22 +86,19 @@ int OpDesc::init_stencil(const Taps& t, int nx, bool seq, std::string& err) {
   width = W;
   const int Wb = pick_width(W);
   int k = 0, nl = 0;
-  if (Wb > 0 && pick_stencil_shape(nx, Wb, seq, k, nl)) {
+  if (Wb > 0 && pick_stencil_shape(nx, Wb, seq, io, k, nl)) {
     kind = OP_STENCIL;
     K = k;
     NL = nl;
     Wbucket = Wb;
     const int ki = k_index(K), wi = width_index(Wb);
-    fn[0] = kt.stencil[0][ki][wi];
-    fn[1] = kt.stencil[1][ki][wi];
-    dense.resize(Wb, 0.0);
-    const int H = std::min(Wb - 1, K);
-    const bool shfl = (Wb - 1 <= K);
-    for (int p = 0; p < 2; ++p) {
-      const size_t el = p == 0 ? sizeof(double) : sizeof(float);
-      shmem[p] = shfl ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el
-                      : 2 * (size_t)H * NL * el;
+    for (int q = 0; q < 2; ++q) {
+      fn[q] = kt.stencil[q][ki][wi][0];
+      fn_io[q] = kt.stencil[q][ki][wi][1];
     }
+    dense.resize(Wb, 0.0);
+    shmem[0] = stencil_lds(nx, K, NL, Wb, sizeof(double));
+    shmem[1] = stencil_lds(nx, K, NL, Wb, sizeof(float));
     if (hipMalloc(&d_taps, dense.size() * sizeof(double)) != hipSuccess) return MGRIT_ENOMEM;
     bytes += dense.size() * sizeof(double);
     if (hipMemcpy(d_taps, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice) !=
@@ -118,8 +136,9 @@ int OpDesc::init_stencil(const Taps& t, int nx, bool seq, std::string& err) {
       return MGRIT_EHIP;
   }
   for (int p = 0; p < 2; ++p)
-    if (fn[p] && shmem[p] > 64 * 1024)
-      if (hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
+    for (KernelFn f : {fn[p], fn_io[p]})
+      if (f && shmem[p] > 64 * 1024 &&
+          hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shmem[p]) != hipSuccess)
         return MGRIT_EHIP;
   return MGRIT_OK;
@@ -157,8 +176,13 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   kind = OP_SDIRK;
   fn[0] = kt.sdirk[0][sdirk_k_index(K)][si];
   fn[1] = kt.sdirk[1][sdirk_k_index(K)][si];
-  shmem[0] = shmem[1] = 0;
+  shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
   nnz = 0;
+  for (int p = 0; p < 2; ++p)
+    if (shmem[p] > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem[p]) != hipSuccess)
+      return MGRIT_EHIP;
   if (hipMalloc(&d_sdirk, sizeof(SdirkDev)) != hipSuccess) return MGRIT_ENOMEM;
   bytes += sizeof(SdirkDev);
   if (hipMemcpy(d_sdirk, &sd, sizeof(SdirkDev), hipMemcpyHostToDevice) != hipSuccess)
@@ -205,7 +229,10 @@ static RelaxArgs base_args(const Plan& P, const OpDesc& op) {
 }
 
 int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int cls) {
-  KernelFn fn = op.fn[prec];
+  // stencil kernels come without per-step memory traffic unless the pass
+  // adds a right-hand side every step or stores every state
+  const bool io = a.rhs_mode == RHS_EVERY || a.mode == MODE_F;
+  KernelFn fn = (op.kind == OP_STENCIL && io) ? op.fn_io[prec] : op.fn[prec];
   if (!fn) return MGRIT_EINVAL;
   RelaxArgs args = a;
   void* kargs[] = {&args};
@@ -516,14 +543,14 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
         else {
           Taps f;
           erk_taps(t, cfl, nx, f);
-          rc = L.op.init_stencil(f, nx, false, err);
+          rc = L.op.init_stencil(f, nx, false, false, err);
         }
       } else {
         Taps f;
         f.off.assign(psi[l - 1].offset, psi[l - 1].offset + psi[l - 1].nnz);
         f.w.assign(psi[l - 1].weight, psi[l - 1].weight + psi[l - 1].nnz);
-        if (l < levels - 1) rc = L.op.init_stencil(f, nx, false, err);
-        else rc = L.seq.init_stencil(f, nx, true, err);
+        if (l < levels - 1) rc = L.op.init_stencil(f, nx, false, true, err);
+        else rc = L.seq.init_stencil(f, nx, true, true, err);
       }
       if (rc) return fail(rc);
       P->bytes += L.op.bytes + L.seq.bytes;

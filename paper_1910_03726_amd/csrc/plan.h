@@ -19,6 +19,7 @@ enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
 struct OpDesc {
   int kind = OP_GENERIC;
   KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
+  KernelFn fn_io[2] = {nullptr, nullptr};  // stencil variants with per-step IO
   size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
   int NL = 0, K = 0;                    // lanes per workgroup, points per lane
   int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
@@ -28,7 +29,7 @@ struct OpDesc {
   void* d_sdirk = nullptr;
   size_t bytes = 0;
 
-  int init_stencil(const Taps& t, int nx, bool seq, std::string& err);
+  int init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& err);
   int init_sdirk(const Tableau& t, double cfl, int nx, std::string& err);
   void release();
   std::string describe() const;

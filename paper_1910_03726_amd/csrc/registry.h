@@ -23,7 +23,7 @@ constexpr int kNumSdirkShapes = 4;
 constexpr int kSdirkShapes[kNumSdirkShapes][2] = {{1, 1}, {2, 1}, {3, 2}, {5, 3}};
 
 struct KernelTable {
-  KernelFn stencil[2][kNumK][kNumWidths] = {};
+  KernelFn stencil[2][kNumK][kNumWidths][2] = {};  // [prec][K][W][per-step IO]
   KernelFn sdirk[2][kNumSdirkK][kNumSdirkShapes] = {};
   KernelFn generic[2] = {};
 };

@@ -45,96 +45,159 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Start state of interval j at points p0..p0+K-1, in FP64.
+// ---------------------------------------------------------------------------
+// Coalesced row traffic through LDS
+// ---------------------------------------------------------------------------
+// Lane l owns local points p = l*K .. l*K+K-1; local point p is the true
+// point (p + sh) mod n_x (the frame shift of the stencil kernels).  Rows go
+// between HBM and LDS with consecutive lanes on consecutive doubles (full
+// cache lines per instruction) and between LDS and each lane's chunk with
+// local point p at stg[p + p/K]: one pad slot per chunk makes the chunk
+// reads and writes free of bank conflicts.
 template <int K>
-__device__ __forceinline__ void start_state(const RelaxArgs& a, int j, int p0,
+struct Stager {
+  double* stg;
+  int nx, NL, lane;
+  __device__ __forceinline__ int slot(int p) const { return p + p / K; }
+  __device__ __forceinline__ int local(int i, int sh) const {
+    int p = i - sh;
+    return p + ((p < 0) ? nx : 0);
+  }
+  // global -> registers in the coalesced layout (element q is true point
+  // lane + q*NL); used to issue a row's loads early
+  __device__ __forceinline__ void fetch(const double* row, double (&r)[K]) const {
+#pragma unroll
+    for (int q = 0; q < K; ++q) r[q] = row[lane + q * NL];
+  }
+  // coalesced registers -> this lane's chunk
+  template <typename T>
+  __device__ __forceinline__ void deliver(const double (&r)[K], int sh, T (&x)[K]) const {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) stg[slot(local(lane + q * NL, sh))] = r[q];
+    __syncthreads();
+    const int b = lane * (K + 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = (T)stg[b + k];
+  }
+  template <typename T>
+  __device__ __forceinline__ void load(const double* row, int sh, T (&x)[K]) const {
+    double r[K];
+    fetch(row, r);
+    deliver(r, sh, x);
+  }
+  template <typename T>
+  __device__ __forceinline__ void store(double* row, int sh, const T (&x)[K]) const {
+    __syncthreads();
+    const int b = lane * (K + 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) stg[b + k] = (double)x[k];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int i = lane + q * NL;
+      row[i] = stg[slot(local(i, sh))];
+    }
+  }
+};
+
+// LDS doubles of the staging area for n_x points in chunks of K.
+__host__ __device__ constexpr int stage_doubles(int nx, int K) { return nx + nx / K; }
+
+// Start state of interval j in FP64 (staged, coalesced).
+template <int K>
+__device__ __forceinline__ void start_state(const RelaxArgs& a, int j, const Stager<K>& S,
                                             double (&v)[K]) {
   if (a.zero_in) {
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = 0.0;
     return;
   }
-  const double* src = a.in + (long long)j * a.in_stride * a.nx + p0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = src[k];
+  S.load(a.in + (long long)j * a.in_stride * a.nx, 0, v);
+  __builtin_amdgcn_sched_barrier(0);  // one row in flight at a time
   if (a.corr) {
-    const double* c = a.corr + (long long)j * a.corr_stride * a.nx + p0;
+    double c[K];
+    S.load(a.corr + (long long)j * a.corr_stride * a.nx, 0, c);
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += c[k];
   }
 }
 
-// Stores after the last step.  `sh` is the frame shift: local point p holds
-// the value of true point (p + sh) mod n_x.
+// Stores after the last step; `sh` is the frame shift of x.
 template <typename T, int K>
-__device__ __forceinline__ void finish(const RelaxArgs& a, int j, int p0, int sh,
+__device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K>& S, int sh,
                                        const T (&x)[K], double* red) {
   const int nx = a.nx;
+  if (a.mode != MODE_FC && a.mode != MODE_RES) return;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (double)x[k];
+  if (a.rhs_mode == RHS_CPOINT) {
+    double g[K];
+    S.load(a.rhs + (long long)(j + 1) * nx, sh, g);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += g[k];
+  }
   if (a.mode == MODE_FC) {
-    double* o = a.out + (long long)(j + a.out_off) * nx;
-    const double* g = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;
+    S.store(a.out + (long long)(j + a.out_off) * nx, sh, v);
+    return;
+  }
+  double rf[K];
+  S.load(a.ref + (long long)(j + 1) * nx, sh, rf);
+  double ss = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int idx = wrap_hi(p0 + k + sh, nx);
-      double v = (double)x[k];
-      if (g) v += g[idx];
-      o[idx] = v;
-    }
-  } else if (a.mode == MODE_RES) {
-    double* o = a.out + (long long)(j + 1) * nx;
-    const double* rf = a.ref + (long long)(j + 1) * nx;
-    const double* g = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;
-    double ss = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int idx = wrap_hi(p0 + k + sh, nx);
-      double v = (double)x[k];
-      if (g) v += g[idx];
-      v -= rf[idx];
-      o[idx] = v;
-      ss += v * v;
-    }
-    if (j == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) a.out[p0 + k] = 0.0;  // r^0 = 0
-    }
-    if (a.partial) {
-      const double s = block_sum(ss, red);
-      if (threadIdx.x == 0) a.partial[j] = s;
-    }
+  for (int k = 0; k < K; ++k) {
+    v[k] -= rf[k];
+    ss += v[k] * v[k];
+  }
+  S.store(a.out + (long long)(j + 1) * nx, sh, v);
+  if (j == 0) {
+    for (int i = S.lane; i < nx; i += S.NL) a.out[i] = 0.0;  // r^0 = 0
+  }
+  if (a.partial) {
+    const double s = block_sum(ss, red);
+    if (threadIdx.x == 0) a.partial[j] = s;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Register-resident periodic stencil
-// ---------------------------------------------------------------------------
-template <typename T, int K, int W>
-__global__ void __launch_bounds__(256) k_stencil(RelaxArgs a) {
-  // H values per lane are published to LDS: all edge values when the halo
-  // reaches past the left neighbour (W-1 > K), else only the wavefront's
-  // last lane publishes its W-1 edge values for the next wavefront.
+// IO = false: no per-step memory traffic (fine-level FC and residual
+// passes); IO = true: right-hand side every step and/or every state stored
+// (coarse levels, interpolation, sequential sweeps).  With IO the next
+// step's right-hand side row is requested one step before it is added.
+//
+// Two ways to apply the stencil, chosen at compile time:
+//  * W-1 <= K (halo within the left neighbour lane): in place, right to
+//    left, halo values by cross-lane permute inside the wavefront and from a
+//    2*H-value LDS slot per wavefront across wavefronts;
+//  * W-1 > K (wide coarse operators): the chunk image of every lane sits in
+//    the staging area (padded layout), each output accumulates while halo
+//    values stream from LDS one at a time (registers ~2K instead of K+W).
+//    The same image feeds the per-step coalesced stores.
+//
+// Dynamic LDS: the staging area (stage_doubles(n_x, K) doubles), followed
+// in the first case by 2*H slots per wavefront.
+template <typename T, int K, int W, bool IO>
+__global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   constexpr bool kShfl = (W - 1 <= K);
   constexpr int H = (W - 1 < K) ? (W - 1) : K;
   constexpr int HW = (W > 1) ? (W - 1) : 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[16];
 
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
   const int j = blockIdx.x;
-  const int p0 = lane * K;
   const int wave = lane >> 6, lw = lane & 63, nwave = NL >> 6;
+  const Stager<K> S{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
+  T* sm = reinterpret_cast<T*>(smem_raw + sizeof(double) * stage_doubles(nx, K));
+  T* img = reinterpret_cast<T*>(S.stg);  // chunk image, padded layout, as T
 
   double v0[K];
-  start_state<K>(a, j, p0, v0);
+  start_state<K>(a, j, S, v0);
   if (a.mode == MODE_F) {
-    double* o = a.out + (long long)j * m * nx + p0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) o[k] = v0[k];
+    S.store(a.out + (long long)j * m * nx, 0, v0);
     if (j == a.nint) return;  // extra block: the last corrected C-point
   } else if (a.mode == MODE_FC && a.write_row0 && j == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) a.out[p0 + k] = v0[k];
+    S.store(a.out, 0, v0);
   }
   T x[K];
 #pragma unroll
@@ -143,14 +206,25 @@ __global__ void __launch_bounds__(256) k_stencil(RelaxArgs a) {
 #pragma unroll
   for (int t = 0; t < W; ++t) tp[t] = (T)a.taps[t];
 
+  const bool every = IO && a.rhs_mode == RHS_EVERY;
+  const bool store_steps = IO && a.mode == MODE_F;
+  double gnext[IO ? K : 1];
+  if constexpr (IO) {
+    if (every && m >= 1) S.fetch(a.rhs + ((long long)j * m + 1) * nx, gnext);
+  }
+  const int b = lane * (K + 1);
+  if constexpr (!kShfl) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) img[b + k] = x[k];
+    __syncthreads();
+  }
+
   int sh = 0;
   for (int s = 1; s <= m; ++s) {
-    if constexpr (W > 1) {
-      T halo[HW];
-      if constexpr (kShfl) {
-        // left neighbour inside the wavefront by cross-lane permute; the
-        // wavefront's lane 0 takes the previous wavefront's edge from LDS
-        // (periodic wrap for the first wavefront).
+    if constexpr (kShfl) {
+      if constexpr (W > 1) {
+        T halo[HW];
         T* slot = sm + (s & 1) * nwave * H;
         if (nwave > 1) {
           if (lw == 63) {
@@ -163,58 +237,82 @@ __global__ void __launch_bounds__(256) k_stencil(RelaxArgs a) {
         const int pw = (wave + nwave - 1) % nwave;
 #pragma unroll
         for (int h = 0; h < W - 1; ++h) {
-          // halo[h] is the point W-1-h to the left of p0: element K-(W-1-h)
-          // of the left neighbour lane
+          // halo[h]: the point W-1-h to the left of lane*K, element
+          // K-(W-1-h) of the left neighbour lane
           const int e = K - (W - 1 - h);
           T v = __shfl(x[e], srcl, 64);
           if (nwave > 1 && lw == 0) v = slot[pw * H + (e - (K - H))];
           halo[h] = v;
         }
+        // in place, right to left: x[k] <- sum_t tp[t] * x[k - t]
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+          T acc = (T)0;
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            const int idx = k - t;
+            const T v = (idx >= 0) ? x[idx >= 0 ? idx : 0] : halo[idx < 0 ? W - 1 + idx : 0];
+            acc = fma(tp[t], v, acc);
+          }
+          x[k] = acc;
+        }
       } else {
-        T* buf = sm + (s & 1) * H * NL;
 #pragma unroll
-        for (int e = 0; e < H; ++e) buf[e * NL + lane] = x[K - H + e];
-        __syncthreads();
-#pragma unroll
-        for (int h = 0; h < W - 1; ++h) {
-          const int d = W - 1 - h;             // distance to the left of p0
-          const int Ld = (d + K - 1) / K;      // lanes to the left
-          const int e = K * Ld - d;            // element in that lane
-          int src = lane - Ld;
-          src += (src < 0) ? NL : 0;
-          halo[h] = buf[e * NL + src];
-        }
-      }
-      // in place, right to left: x[k] <- sum_t tp[t] * x[k - t]
-#pragma unroll
-      for (int k = K - 1; k >= 0; --k) {
-        T acc = (T)0;
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const int idx = k - t;
-          const T v = (idx >= 0) ? x[idx >= 0 ? idx : 0] : halo[idx < 0 ? W - 1 + idx : 0];
-          acc = fma(tp[t], v, acc);
-        }
-        x[k] = acc;
+        for (int k = 0; k < K; ++k) x[k] *= tp[0];
       }
     } else {
+      // stream the window position q (relative to lane*K) from the image
+      T acc[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) x[k] *= tp[0];
+      for (int k = 0; k < K; ++k) acc[k] = (T)0;
+#pragma unroll
+      for (int q = -(W - 1); q < K; ++q) {
+        T v;
+        if (q >= 0) {
+          v = x[q >= 0 ? q : 0];
+        } else {
+          int p = lane * K + q;
+          p += (p < 0) ? nx : 0;
+          v = img[S.slot(p)];
+        }
+#pragma unroll
+        for (int k = (q > 0 ? q : 0); k < K && k < q + W; ++k) acc[k] = fma(tp[k - q], v, acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) x[k] = acc[k];
     }
-    sh += a.omin;
-    sh = wrap_hi(sh, nx);
-    if (a.rhs_mode == RHS_EVERY) {
-      const double* g = a.rhs + ((long long)j * m + s) * nx;
+    sh = wrap_hi(sh + a.omin, nx);
+    if constexpr (IO) {
+      if (every) {
+        T g[K];
+        S.deliver(gnext, sh, g);
+        if (s < m) S.fetch(a.rhs + ((long long)j * m + s + 1) * nx, gnext);
 #pragma unroll
-      for (int k = 0; k < K; ++k) x[k] += (T)g[wrap_hi(p0 + k + sh, nx)];
+        for (int k = 0; k < K; ++k) x[k] += g[k];
+      }
     }
-    if (a.mode == MODE_F && (s < m || a.write_last)) {
-      double* o = a.out + ((long long)j * m + s) * nx;
+    if constexpr (!kShfl) {
+      // new image: the next step's halo source and the coalesced store
+      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < K; ++k) o[wrap_hi(p0 + k + sh, nx)] = (double)x[k];
+      for (int k = 0; k < K; ++k) img[b + k] = x[k];
+      __syncthreads();
+      if constexpr (IO) {
+        if (store_steps && (s < m || a.write_last)) {
+          double* row = a.out + ((long long)j * m + s) * nx;
+#pragma unroll
+          for (int q = 0; q < K; ++q) {
+            const int i = lane + q * NL;
+            row[i] = (double)img[S.slot(S.local(i, sh))];
+          }
+        }
+      }
+    } else if constexpr (IO) {
+      if (store_steps && (s < m || a.write_last))
+        S.store(a.out + ((long long)j * m + s) * nx, sh, x);
     }
   }
-  finish<T, K>(a, j, p0, sh, x, red);
+  finish<T, K>(a, j, S, sh, x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -379,25 +477,24 @@ __device__ __forceinline__ void rec_apply(T (&y)[K], const RecDev& f, const T (&
   }
 }
 
+// Dynamic LDS: the staging area (stage_doubles(n_x, K) doubles).
 template <typename T, int K, int S, int NF>
 __global__ void __launch_bounds__(512) k_sdirk(RelaxArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ T scan[2][32];
   __shared__ double red[16];
   const SdirkDev* sd = reinterpret_cast<const SdirkDev*>(a.sdirk);
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
   const int j = blockIdx.x;
-  const int p0 = lane * K;
+  const Stager<K> St{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
 
   double v0[K];
-  start_state<K>(a, j, p0, v0);
+  start_state<K>(a, j, St, v0);
   if (a.mode == MODE_F) {
-    double* o = a.out + (long long)j * m * nx + p0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) o[k] = v0[k];
+    St.store(a.out + (long long)j * m * nx, 0, v0);
     if (j == a.nint) return;
   } else if (a.mode == MODE_FC && a.write_row0 && j == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) a.out[p0 + k] = v0[k];
+    St.store(a.out, 0, v0);
   }
   // per-lane scan matrices of each factor
   T Pw[NF][4], Pl[NF][4];
@@ -449,17 +546,15 @@ __global__ void __launch_bounds__(512) k_sdirk(RelaxArgs a) {
       }
     }
     if (a.rhs_mode == RHS_EVERY) {
-      const double* g = a.rhs + ((long long)j * m + s) * nx + p0;
+      T g[K];
+      St.load(a.rhs + ((long long)j * m + s) * nx, 0, g);
 #pragma unroll
-      for (int k = 0; k < K; ++k) u[k] += (T)g[k];
+      for (int k = 0; k < K; ++k) u[k] += g[k];
     }
-    if (a.mode == MODE_F && (s < m || a.write_last)) {
-      double* o = a.out + ((long long)j * m + s) * nx + p0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) o[k] = (double)u[k];
-    }
+    if (a.mode == MODE_F && (s < m || a.write_last))
+      St.store(a.out + ((long long)j * m + s) * nx, 0, u);
   }
-  finish<T, K>(a, j, p0, 0, u, red);
+  finish<T, K>(a, j, St, 0, u, red);
 }
 
 }  // namespace mgr
