@@ -78,7 +78,26 @@ def _fine_nnz(w):
     return len(off)
 
 
-def roofline(P, w, u0, uinit, torch):
+def measured_traffic(workload):
+    """HBM bytes per launch of the fine relaxation kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    changed since the counters were taken (hash recorded in the summary)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")
+    src = os.path.join(ROOT, "paper_1910_03726_amd", "csrc", "relax_kernels.h")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    rec, val = None, None
+    for line in open(path):
+        if line.startswith("kernel source (relax_kernels.h) sha256[:16]:"):
+            rec = line.rsplit(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            val = float(line.split(":", 1)[1])
+    return val if rec == sha else None
+
+
+def roofline(P, w, u0, uinit, torch, workload):
     """Fine relaxation kernel: algorithmic bytes and flops over its launches."""
     P.set_profiling(True)
     r = P.solve(u0, uinit, tol=TOL, maxit=100, out="none")
@@ -102,7 +121,8 @@ def roofline(P, w, u0, uinit, torch):
     t_alu = flops_total / (FP64_PEAK_TFS * 1e12) if flops_total else 0.0
     out = {"bound": "hbm" if t_hbm >= t_alu else "alu",
            "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic(workload),
            "kernel": "k_stencil (fine-level FC and residual passes)",
            "launches": launches, "avg_launch_ms": round(avg_ms, 5),
            "bytes_per_launch": bytes_total / launches,
@@ -174,6 +194,9 @@ def main():
     ap.add_argument("--workload", default=MAIN)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB three times "
+                         "(reference for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -184,6 +207,14 @@ def main():
     from paper_1910_03726_amd import inputs
     torch.cuda.init()
     w = dict(inputs.WORKLOADS[a.workload])
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     P, psi = _plan(w)
     u0, uinit = _inputs(w, torch)
     dt, r = _timed_solves(P, u0, uinit, a.steps, a.warmup, torch)
@@ -199,7 +230,7 @@ def main():
                        "psi_nnz": [len(o) for o, _ in psi]},
             "iterations": r.iters, "final_residual": r.hist[-1],
             "kernels": P.describe()}
-    line["roofline"] = roofline(P, w, u0, uinit, torch)
+    line["roofline"] = roofline(P, w, u0, uinit, torch, a.workload)
     tseq = gpu_sequential(P, w, u0, torch)
     line["gpu_sequential"] = {"ms": round(tseq * 1e3, 3),
                               "dof_per_s": w["nx"] * w["nt"] / tseq,
