@@ -167,6 +167,97 @@ def gpu_sequential(P, w, u0, torch):
     return time.perf_counter() - t0
 
 
+def _serve_run(reqs, u0s, arrivals, slots, setup_threads, budget):
+    """Submit reqs at their arrival times (seconds after start); return
+    (results, makespan seconds, server stats)."""
+    import threading
+    from paper_1910_03726_amd import mgrit as M
+    S = M.Server(budget, slots=slots, setup_threads=setup_threads, max_bypass=8)
+    ids = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for k, q in enumerate(reqs):
+            if arrivals is not None:
+                dt = arrivals[k] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            ids[k] = S.submit(q["nx"], q["nt"], q["scheme"], q["cfl"], q["m"], u0s[k],
+                              precision=q["precision"], seed=q["init_seed"])
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = []
+    for k, q in enumerate(reqs):
+        while ids[k] is None:
+            time.sleep(0.0005)
+        r, _ = S.wait(ids[k], q["nx"])
+        res.append(r)
+    th.join()
+    makespan = time.perf_counter() - t0
+    st = S.stats()
+    S.close()
+    return res, makespan, st
+
+
+def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
+    """The serving mix: saturated throughput, then Poisson arrivals at 80% of
+    it (p50/p99 latency); the plain FP64 per-solve form on a 10% sample."""
+    import numpy as np
+    from paper_1910_03726_amd import inputs, mgrit as M
+    reqs = inputs.serving_requests(n, seed=7)
+    u0s = [inputs.request_u0(q) for q in reqs]
+    dof = sum(q["nx"] * q["nt"] for q in reqs)
+    budget = budget_gib << 30
+    res, span, st = _serve_run(reqs, u0s, None, slots, setup_threads, budget)
+    ok = sum(r.status == M.OK for r in res)
+    rate = n / span
+    arr = inputs.poisson_arrivals(n, 0.8 * rate, seed=7)
+    res2, span2, st2 = _serve_run(reqs, u0s, arr, slots, setup_threads, budget)
+    lat = np.array([r.latency_ms for r in res2])
+    lat_sat = np.array([r.latency_ms for r in res])
+    # plain per-solve FP64: fresh setup and plan per request, one at a time
+    sample = reqs[::10]
+    t0 = time.perf_counter()
+    sdof = 0
+    for q in sample:
+        psi, _ = M.psi_optimize(q["scheme"], q["cfl"], q["nx"], q["m"],
+                                _auto_levels(q["nt"], q["m"]))
+        with M.Plan(q["nx"], q["nt"], q["cfl"], q["scheme"], q["m"],
+                    _auto_levels(q["nt"], q["m"]), psi) as P:
+            P.set_seed(q["init_seed"])
+            u0 = torch.tensor(inputs.request_u0(q), dtype=torch.float64, device="cuda")
+            P.solve(u0, None, tol=TOL, maxit=100, out="final")
+        sdof += q["nx"] * q["nt"]
+    tb = time.perf_counter() - t0
+    return {"requests": n, "completed_ok": ok, "slots": slots,
+            "setup_threads": setup_threads, "hbm_budget_gib": budget_gib,
+            "hbm_peak_gib": round(st.hbm_peak / (1 << 30), 3),
+            "psi_cache_hits": st.psi_cache_hits, "psi_cache_misses": st.psi_cache_misses,
+            "saturated": {"makespan_s": round(span, 3), "requests_per_s": round(rate, 2),
+                          "dof_per_s": dof / span,
+                          "p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
+            "poisson_80pct": {"rate_per_s": round(0.8 * rate, 2),
+                              "makespan_s": round(span2, 3),
+                              "dof_per_s": dof / span2,
+                              "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                              "p99_ms": round(float(np.percentile(lat, 99)), 3)},
+            "per_solve_fp64": {"sample": f"{len(sample)} of {n} requests (every 10th), "
+                                         "one at a time, fresh setup and plan each",
+                               "dof_per_s": sdof / tb,
+                               "ms_per_request": round(1e3 * tb / len(sample), 3)},
+            "serving_speedup_vs_per_solve": round((dof / span) / (sdof / tb), 2)}
+
+
+def _auto_levels(nt, m):
+    L, span = 2, m * m
+    while nt % span == 0 and nt // span >= 8:
+        L += 1
+        span *= m
+    return L
+
+
 def workload_line(name, steps, warmup, torch, precision=None):
     from paper_1910_03726_amd import inputs
     w = dict(inputs.WORKLOADS[name])
@@ -194,6 +285,8 @@ def main():
     ap.add_argument("--workload", default=MAIN)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--serve", type=int, default=2000, metavar="N",
+                    help="requests in the serving measurement (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times "
                          "(reference for HBM byte counters)")
@@ -248,6 +341,8 @@ def main():
             except Exception as e:  # report, keep the main line
                 extra[name] = {"error": str(e)}
         line["workloads"] = extra
+    if a.serve > 0 and not a.no_extra:
+        line["serving"] = serving(a.serve, torch)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)

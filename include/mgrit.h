@@ -195,6 +195,11 @@ int phi_apply_batch(mgrit_plan_t plan, const double* in_dev, double* out_dev,
 /* Device bytes the plan holds (its HBM footprint, for admission). */
 int mgrit_plan_bytes(mgrit_plan_t plan, size_t* hbm_bytes);
 
+/* Upper bound of the device bytes mgrit_plan_create would allocate for
+ * these sizes (no allocation; host only). */
+int mgrit_plan_estimate_bytes(int nx, int nt, int m, int levels, int precision,
+                              size_t* bytes);
+
 /* Seed of the U[0,1) initial iterate used when uinit_dev is NULL. */
 int mgrit_plan_set_seed(mgrit_plan_t plan, unsigned long long seed);
 

@@ -32,6 +32,7 @@ def _jobs():
     objs = []
     objs.append(("g++", os.path.join(CSRC, "setup.cpp"), "setup.o", []))
     objs.append((HIPCC, os.path.join(CSRC, "plan.cpp"), "plan.o", ["-x", "hip"]))
+    objs.append((HIPCC, os.path.join(CSRC, "serve.cpp"), "serve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
     for prec in (0, 1):
         objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),
@@ -61,7 +62,7 @@ def build(jobs=None, verbose=False):
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, work))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

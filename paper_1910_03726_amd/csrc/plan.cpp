@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -401,6 +402,24 @@ int Plan::cycle(int l, const double* g, bool zero, int kind, int prec) {
 
 }  // namespace mgr
 
+namespace mgr {
+// Device bytes of a plan's space-time arrays (everything but the taps).
+size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
+  const size_t row = (size_t)nx * sizeof(double);
+  const long long nc = nt / m;
+  size_t b = 3 * (size_t)(nc + 1) * row;                       // V_a, V_b, R_1
+  if (precision == MGRIT_FP32_RELAX) b += 2 * (size_t)(nc + 1) * row;  // U, R_out
+  long long n = nt;
+  for (int l = 1; l < levels; ++l) {
+    n /= m;
+    b += (size_t)(n + 1) * row;                                 // X_l
+    if (l < levels - 1) b += 2 * (size_t)(n / m + 1) * row;     // V_l, R_l
+  }
+  b += (size_t)(nc + 2) * sizeof(double);                       // partials, norm
+  return b;
+}
+}  // namespace mgr
+
 using namespace mgr;
 
 // ---------------------------------------------------------------------------
@@ -479,15 +498,17 @@ int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels, int ru
   return rc;
 }
 
+// The current device must be a gfx950; the answer is cached per device.
 static int check_device() {
-  int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return MGRIT_ENODEV;
+  static std::atomic<int> known[64];  // 0 unknown, 1 gfx950, 2 other
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return MGRIT_ENODEV;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MGRIT_ENODEV;
+  if (dev < 64 && known[dev].load() != 0) return known[dev].load() == 1 ? MGRIT_OK : MGRIT_ENODEV;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MGRIT_ENODEV;
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MGRIT_ENODEV;
-  return MGRIT_OK;
+  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  if (dev < 64) known[dev].store(ok ? 1 : 2);
+  return ok ? MGRIT_OK : MGRIT_ENODEV;
 }
 
 int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
@@ -615,6 +636,14 @@ void mgrit_destroy(mgrit_plan_t plan) {
   }
   for (auto e : P->event_pool) (void)hipEventDestroy(e);
   delete P;
+}
+
+int mgrit_plan_estimate_bytes(int nx, int nt, int m, int levels, int precision,
+                              size_t* bytes) {
+  if (!bytes || nx < 1 || nt < 1 || m < 2 || levels < 2) return MGRIT_EINVAL;
+  // space-time arrays plus a bound on the per-level taps and stage data
+  *bytes = plan_state_bytes(nx, nt, m, levels, precision) + (size_t)levels * 64 * 1024;
+  return MGRIT_OK;
 }
 
 int mgrit_plan_bytes(mgrit_plan_t plan, size_t* b) {

@@ -1,0 +1,350 @@
+// Continuous-batching server of libmgrit (include/mgrit_serve.h).
+//
+// Threads: `setup_threads` workers compute coarse operators on the host
+// (with a cache); `slots` workers each own a HIP stream and run one admitted
+// request at a time on it, so the kernels of all resident requests overlap
+// on the device.  Admission (under one mutex) happens whenever a request
+// becomes ready or a slot frees its memory.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mgrit.h"
+#include "../../include/mgrit_serve.h"
+#include "setup.h"
+
+namespace mgr {
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  long long id = 0;
+  mgrit_request r = {};
+  std::vector<double> u0;
+  std::vector<Taps> psi;
+  int levels = 0;
+  size_t bytes = 0;
+  enum { SETUP, READY, RUNNING, DONE } state = SETUP;
+  int bypassed = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  mgrit_result res = {};
+  std::vector<double> ufinal;
+};
+
+using PsiKey = std::tuple<int, unsigned long long, int, int, int>;
+
+struct Server {
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<long long, std::shared_ptr<Req>> reqs;
+  std::deque<std::shared_ptr<Req>> setup_q, ready_q, run_q;
+  std::map<PsiKey, std::vector<Taps>> psi_cache;
+  long long next_id = 1, submitted = 0, completed = 0, hits = 0, misses = 0;
+  size_t budget = 0, in_use = 0, peak = 0;
+  int free_slots = 0, max_bypass = 0, device = 0;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+
+  // Admit ready requests in submission order while slots and budget allow;
+  // a request that does not fit may be passed max_bypass times.  Caller
+  // holds `mu`.
+  void try_admit() {
+    for (auto it = ready_q.begin(); it != ready_q.end() && free_slots > 0;) {
+      Req& q = **it;
+      if (in_use + q.bytes <= budget) {
+        in_use += q.bytes;
+        if (in_use > peak) peak = in_use;
+        --free_slots;
+        q.state = Req::RUNNING;
+        q.t_admit = now_ms();
+        run_q.push_back(*it);
+        it = ready_q.erase(it);
+        cv.notify_all();
+        continue;
+      }
+      if (q.bypassed >= max_bypass) break;  // nobody may pass it any more
+      ++q.bypassed;
+      ++it;
+    }
+  }
+
+  void setup_loop() {
+    for (;;) {
+      std::shared_ptr<Req> q;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stopping || !setup_q.empty(); });
+        if (setup_q.empty()) return;
+        q = setup_q.front();
+        setup_q.pop_front();
+      }
+      const mgrit_request& r = q->r;
+      PsiKey key{r.scheme, 0ULL, r.nx, r.m, q->levels};
+      std::memcpy(&std::get<1>(key), &r.cfl, sizeof(double));
+      std::vector<Taps> psi;
+      bool hit = false;
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        auto f = psi_cache.find(key);
+        if (f != psi_cache.end()) {
+          psi = f->second;
+          hit = true;
+          ++hits;
+        }
+      }
+      int rc = MGRIT_OK;
+      if (!hit) {
+        double mi = 0.0;
+        try {
+          rc = psi_hierarchy(r.scheme, r.cfl, r.nx, r.m, q->levels, MGRIT_PSI_AUTO, nullptr,
+                             0.0, psi, mi);
+        } catch (...) {
+          rc = MGRIT_ENOMEM;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ++misses;
+        if (rc == MGRIT_OK) psi_cache[key] = psi;
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != MGRIT_OK) {
+        q->res.status = rc;
+        q->state = Req::DONE;
+        q->t_done = now_ms();
+        ++completed;
+      } else {
+        q->psi = std::move(psi);
+        q->state = Req::READY;
+        auto pos = ready_q.begin();
+        while (pos != ready_q.end() && (*pos)->id < q->id) ++pos;
+        ready_q.insert(pos, q);
+        try_admit();
+      }
+      cv.notify_all();
+    }
+  }
+
+  void slot_loop() {
+    (void)hipSetDevice(device);
+    hipStream_t stream = nullptr;
+    if (hipStreamCreate(&stream) != hipSuccess) stream = nullptr;
+    for (;;) {
+      std::shared_ptr<Req> q;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stopping || !run_q.empty(); });
+        if (run_q.empty()) break;
+        q = run_q.front();
+        run_q.pop_front();
+      }
+      run(*q, stream);
+      std::lock_guard<std::mutex> lk(mu);
+      in_use -= q->bytes;
+      ++free_slots;
+      q->state = Req::DONE;
+      q->t_done = now_ms();
+      ++completed;
+      try_admit();
+      cv.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+
+  void run(Req& q, hipStream_t stream) {
+    const mgrit_request& r = q.r;
+    std::vector<mgrit_taps> taps(q.psi.size());
+    for (size_t l = 0; l < q.psi.size(); ++l) {
+      taps[l].nnz = (int)q.psi[l].off.size();
+      taps[l].offset = q.psi[l].off.data();
+      taps[l].weight = q.psi[l].w.data();
+    }
+    mgrit_plan_t plan = nullptr;
+    int rc = mgrit_plan_create(&plan, r.nx, r.nt, r.alpha, r.cfl, r.scheme, r.m, q.levels,
+                               taps.data(), r.cycle, r.relax, r.precision, stream);
+    q.res.status = rc;
+    if (rc != MGRIT_OK) return;
+    double* dev = nullptr;
+    size_t row = (size_t)r.nx * sizeof(double);
+    if (hipMalloc((void**)&dev, 2 * row) != hipSuccess) {
+      q.res.status = MGRIT_ENOMEM;
+      mgrit_destroy(plan);
+      return;
+    }
+    size_t pb = 0;
+    mgrit_plan_bytes(plan, &pb);
+    q.res.hbm_bytes = pb + 2 * row;
+    if (hipMemcpyAsync(dev, q.u0.data(), row, hipMemcpyHostToDevice, stream) != hipSuccess) {
+      q.res.status = MGRIT_EHIP;
+    } else {
+      mgrit_plan_set_seed(plan, r.seed);
+      int it = 0;
+      rc = mgrit_solve(plan, dev, nullptr, r.tol, r.maxit, dev + r.nx, MGRIT_OUT_FINAL,
+                       nullptr, &it);
+      mgrit_stats st;
+      mgrit_get_stats(plan, &st);
+      q.res.status = rc;
+      q.res.iterations = it;
+      q.res.final_residual = st.final_residual;
+      q.ufinal.resize(r.nx);
+      if (hipMemcpyAsync(q.ufinal.data(), dev + r.nx, row, hipMemcpyDeviceToHost, stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        q.res.status = MGRIT_EHIP;
+    }
+    (void)hipFree(dev);
+    mgrit_destroy(plan);
+  }
+};
+
+static int auto_levels(int nt, int m) {
+  int L = 2;
+  long long span = (long long)m * m;  // m^(L) for the candidate L+1 levels
+  while (nt % span == 0 && nt / span >= 8) {
+    ++L;
+    span *= m;
+  }
+  return L;
+}
+
+}  // namespace mgr
+
+using namespace mgr;
+
+extern "C" {
+
+int mgrit_server_create(mgrit_server_t* out, size_t budget, int slots, int setup_threads,
+                        int max_bypass) {
+  if (!out || slots < 1 || setup_threads < 1 || max_bypass < 0 || budget == 0)
+    return MGRIT_EINVAL;
+  *out = nullptr;
+  Server* S = new (std::nothrow) Server();
+  if (!S) return MGRIT_ENOMEM;
+  S->budget = budget;
+  S->free_slots = slots;
+  S->max_bypass = max_bypass;
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    return MGRIT_ENODEV;
+  }
+  try {
+    for (int i = 0; i < setup_threads; ++i) S->workers.emplace_back([S] { S->setup_loop(); });
+    for (int i = 0; i < slots; ++i) S->workers.emplace_back([S] { S->slot_loop(); });
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stopping = true;
+    }
+    S->cv.notify_all();
+    for (auto& t : S->workers)
+      if (t.joinable()) t.join();
+    delete S;
+    return MGRIT_ENOMEM;
+  }
+  *out = reinterpret_cast<mgrit_server_t>(S);
+  return MGRIT_OK;
+}
+
+int mgrit_server_submit(mgrit_server_t server, const mgrit_request* r, long long* id) {
+  if (!server || !r || !id || !r->u0 || r->nx < 2 || r->nt < 1 || r->m < 2 ||
+      r->maxit < 0 || !(r->tol >= 0.0) || !(r->cfl > 0.0) || !(r->alpha > 0.0))
+    return MGRIT_EINVAL;
+  Server* S = reinterpret_cast<Server*>(server);
+  const int levels = r->levels > 0 ? r->levels : auto_levels(r->nt, r->m);
+  long long span = 1;
+  for (int l = 1; l < levels; ++l) span *= r->m;
+  if (r->nt % span) return MGRIT_EINVAL;
+  size_t bytes = 0;
+  if (mgrit_plan_estimate_bytes(r->nx, r->nt, r->m, levels, r->precision, &bytes) != MGRIT_OK)
+    return MGRIT_EINVAL;
+  bytes += 2 * (size_t)r->nx * sizeof(double);
+  if (bytes > S->budget) return MGRIT_EBUSY;
+  auto q = std::make_shared<Req>();
+  q->r = *r;
+  q->u0.assign(r->u0, r->u0 + r->nx);
+  q->r.u0 = nullptr;
+  q->levels = levels;
+  q->bytes = bytes;
+  q->t_submit = now_ms();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    q->id = S->next_id++;
+    q->res.id = q->id;
+    q->res.levels = levels;
+    S->reqs[q->id] = q;
+    S->setup_q.push_back(q);
+    ++S->submitted;
+  }
+  S->cv.notify_all();
+  *id = q->id;
+  return MGRIT_OK;
+}
+
+int mgrit_server_wait(mgrit_server_t server, long long id, int timeout_ms, mgrit_result* res,
+                      double* u_final) {
+  if (!server) return MGRIT_EINVAL;
+  Server* S = reinterpret_cast<Server*>(server);
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto f = S->reqs.find(id);
+  if (f == S->reqs.end()) return MGRIT_EINVAL;
+  std::shared_ptr<Req> q = f->second;
+  auto done = [&] { return q->state == Req::DONE; };
+  if (timeout_ms < 0) S->cv.wait(lk, done);
+  else if (!S->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+    return MGRIT_EBUSY;
+  q->res.queue_ms = q->t_admit > 0 ? q->t_admit - q->t_submit : q->t_done - q->t_submit;
+  q->res.run_ms = q->t_admit > 0 ? q->t_done - q->t_admit : 0.0;
+  q->res.latency_ms = q->t_done - q->t_submit;
+  if (res) *res = q->res;
+  if (u_final && q->ufinal.size() == (size_t)q->r.nx)
+    std::memcpy(u_final, q->ufinal.data(), q->ufinal.size() * sizeof(double));
+  S->reqs.erase(f);
+  return MGRIT_OK;
+}
+
+int mgrit_server_get_stats(mgrit_server_t server, mgrit_server_stats* st) {
+  if (!server || !st) return MGRIT_EINVAL;
+  Server* S = reinterpret_cast<Server*>(server);
+  std::lock_guard<std::mutex> lk(S->mu);
+  st->submitted = S->submitted;
+  st->completed = S->completed;
+  long long active = 0, waiting = 0;
+  for (auto& kv : S->reqs) {
+    if (kv.second->state == Req::RUNNING) ++active;
+    if (kv.second->state == Req::SETUP || kv.second->state == Req::READY) ++waiting;
+  }
+  st->active = active;
+  st->waiting = waiting;
+  st->hbm_in_use = S->in_use;
+  st->hbm_peak = S->peak;
+  st->hbm_budget = S->budget;
+  st->psi_cache_hits = S->hits;
+  st->psi_cache_misses = S->misses;
+  return MGRIT_OK;
+}
+
+void mgrit_server_destroy(mgrit_server_t server) {
+  if (!server) return;
+  Server* S = reinterpret_cast<Server*>(server);
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv.wait(lk, [&] { return S->completed >= S->submitted; });
+    S->stopping = true;
+  }
+  S->cv.notify_all();
+  for (auto& t : S->workers)
+    if (t.joinable()) t.join();
+  delete S;
+}
+
+}  // extern "C"

@@ -90,3 +90,35 @@ WORKLOADS = {
 def workload_u0(w):
     return fourier_u0(w["nx"], w["u0"]["nmodes"], w["u0"]["seed"],
                       w["u0"]["decay"])
+
+
+def serving_requests(n, seed=7, nx_exps=range(8, 14), nt_exps=range(10, 16),
+                     orders=(1, 3, 5), ms=(4, 8)):
+    """The serving mix: n requests with n_x = 2^a (a in nx_exps), n_t = 2^b
+    (b in nt_exps), ERKp+Up with p in orders, CFL fraction U[0.5, 0.9] of the
+    Table 1 limit, m in ms, FP32 relaxation or FP64 with probability 1/2 each,
+    u0 = 8 seeded Fourier modes, and a seed for the initial iterate.
+    Arrival times are drawn separately (``poisson_arrivals``)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        p = int(rng.choice(orders))
+        frac = float(rng.uniform(0.5, 0.9))
+        out.append(dict(
+            nx=int(2 ** rng.choice(list(nx_exps))),
+            nt=int(2 ** rng.choice(list(nt_exps))),
+            scheme=f"ERK{p}", p=p, cfl=erk_cfl(p, frac), cfl_fraction=frac,
+            m=int(rng.choice(ms)),
+            precision="fp32" if rng.random() < 0.5 else "fp64",
+            u0_seed=int(rng.integers(1 << 31)), init_seed=int(rng.integers(1, 1 << 62))))
+    return out
+
+
+def poisson_arrivals(n, rate, seed=7):
+    """Arrival times (seconds) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed + 1)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def request_u0(req):
+    return fourier_u0(req["nx"], 8, req["u0_seed"])

@@ -52,6 +52,31 @@ class Profile(ctypes.Structure):
                 ("fine_dof_steps", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("nt", ctypes.c_int), ("scheme", ctypes.c_int),
+                ("m", ctypes.c_int), ("levels", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("relax", ctypes.c_int), ("precision", ctypes.c_int),
+                ("alpha", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("seed", ctypes.c_ulonglong), ("u0", ctypes.POINTER(ctypes.c_double))]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_longlong), ("status", ctypes.c_int),
+                ("iterations", ctypes.c_int), ("levels", ctypes.c_int),
+                ("final_residual", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("hbm_bytes", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong),
+                ("active", ctypes.c_longlong), ("waiting", ctypes.c_longlong),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("hbm_budget", ctypes.c_size_t), ("psi_cache_hits", ctypes.c_longlong),
+                ("psi_cache_misses", ctypes.c_longlong)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
@@ -76,6 +101,15 @@ _SIGS = {
     "mgrit_operator_complexity": (_I, [_P, ctypes.POINTER(_D)]),
     "mgrit_plan_describe": (ctypes.c_char_p, [_P]),
     "mgrit_destroy": (None, [_P]),
+    "mgrit_plan_estimate_bytes": (_I, [_I, _I, _I, _I, _I,
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "mgrit_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _I, _I]),
+    "mgrit_server_submit": (_I, [_P, ctypes.POINTER(Request),
+                                 ctypes.POINTER(ctypes.c_longlong)]),
+    "mgrit_server_wait": (_I, [_P, ctypes.c_longlong, _I, ctypes.POINTER(Result),
+                               ctypes.POINTER(_D)]),
+    "mgrit_server_get_stats": (_I, [_P, ctypes.POINTER(ServerStats)]),
+    "mgrit_server_destroy": (None, [_P]),
 }
 
 
@@ -83,6 +117,14 @@ def lib():
     """The loaded libmgrit.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # PyTorch-ROCm ships its own HIP runtime with the same soname
+        # (libamdhip64.so.7).  Loading torch first makes libmgrit bind to that
+        # runtime, so the process has one HIP runtime and torch's streams and
+        # allocations are the library's.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1910_03726_amd.build`")
@@ -282,3 +324,67 @@ class Plan:
 
     def describe(self):
         return lib().mgrit_plan_describe(self._h).decode()
+
+
+def estimate_bytes(nx, nt, m, levels, precision="fp64"):
+    v = ctypes.c_size_t()
+    _check(lib().mgrit_plan_estimate_bytes(nx, nt, m, levels, PRECISION[precision],
+                                           ctypes.byref(v)), "mgrit_plan_estimate_bytes")
+    return v.value
+
+
+class Server:
+    """Continuous-batching server (include/mgrit_serve.h)."""
+
+    def __init__(self, hbm_budget, slots=8, setup_threads=8, max_bypass=4):
+        h = _P()
+        _check(lib().mgrit_server_create(ctypes.byref(h), int(hbm_budget), slots,
+                                         setup_threads, max_bypass), "mgrit_server_create")
+        self._h = h
+
+    def submit(self, nx, nt, scheme, cfl, m, u0, levels=0, cycle="V", relax="FCF",
+               precision="fp64", tol=1e-10, maxit=100, seed=1, alpha=1.0):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        if u0.size != nx:
+            raise ValueError("u0 must hold nx values")
+        r = Request(nx, nt, _scheme(scheme), m, levels, CYCLES[cycle], RELAX[relax],
+                    PRECISION[precision], alpha, cfl, tol, maxit, seed,
+                    u0.ctypes.data_as(ctypes.POINTER(_D)))
+        i = ctypes.c_longlong()
+        _check(lib().mgrit_server_submit(self._h, ctypes.byref(r), ctypes.byref(i)),
+               "mgrit_server_submit")
+        return i.value
+
+    def wait(self, rid, nx, timeout_ms=-1):
+        """(Result, u_final ndarray) or None on timeout."""
+        res = Result()
+        u = np.empty(nx)
+        rc = lib().mgrit_server_wait(self._h, rid, timeout_ms, ctypes.byref(res),
+                                     u.ctypes.data_as(ctypes.POINTER(_D)))
+        if rc == EBUSY:
+            return None
+        _check(rc, "mgrit_server_wait")
+        return res, u
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().mgrit_server_get_stats(self._h, ctypes.byref(st)),
+               "mgrit_server_get_stats")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgrit_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
