@@ -10,9 +10,11 @@
  *               n_x, m and number of levels);
  *   admit    -> when a slot is free and the plan's device footprint
  *               (mgrit_plan_estimate_bytes) fits the HBM budget next to the
- *               plans already resident; requests are admitted in submission
- *               order, a later request may pass one that does not fit yet
- *               at most `max_bypass` times before admission waits for it;
+ *               plans already resident; requests whose setup is done are
+ *               admitted in submission order, a later request may pass one
+ *               that does not fit yet at most `max_bypass` times before
+ *               admission waits for it (setup itself runs on several threads,
+ *               so a request may become ready before an earlier one);
  *   run      -> on the slot's own HIP stream, so the kernels of all
  *               admitted requests overlap on the device; the solve state
  *               stays in device memory until the request completes;
@@ -58,6 +60,8 @@ typedef struct {
     double run_ms;       /* admit -> complete                                 */
     double latency_ms;   /* submit -> complete                                */
     size_t hbm_bytes;    /* device bytes the request held while resident      */
+    long long admit_seq; /* 0-based rank of its admission on this server, -1
+                            if it never ran (setup error)                   */
 } mgrit_result;
 
 typedef struct {

@@ -25,10 +25,11 @@ namespace mgr {
 // kernel selection
 // ---------------------------------------------------------------------------
 // LDS bytes of k_stencil for n_x, chunk K, NL lanes, compiled width Wb.
-static size_t stencil_lds(int nx, int K, int NL, int Wb, size_t el) {
+static size_t stencil_lds(int nx, int K, int NL, int Wb, size_t el, bool io) {
   const int H = std::min(Wb - 1, K);
   const size_t stage = sizeof(double) * (size_t)(nx + nx / K);
-  return stage + ((Wb - 1 <= K) ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el : 0);
+  return stage * (io ? 2 : 1) +
+         ((Wb - 1 <= K) ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el : 0);
 }
 
 // Largest chunk K whose k_stencil<double,K,Wb,io> instantiation compiles
@@ -56,7 +57,7 @@ static bool pick_stencil_shape(int nx, int Wb, bool seq, bool io, int& K, int& N
     const int nl = nx / k;
     if (nl % 64 || nl > 512 || nl < 64) continue;
     if (Wb - 1 > nx) continue;
-    if (stencil_lds(nx, k, nl, Wb, sizeof(double)) > 160 * 1024) continue;
+    if (stencil_lds(nx, k, nl, Wb, sizeof(double), true) > 160 * 1024) continue;
     if (fallbackK < 0) fallbackK = k;  // kKs ascends: the shortest valid chunk
     if (k > kmax) continue;
     if (seq) {
@@ -98,8 +99,10 @@ int OpDesc::init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& 
       fn_io[q] = kt.stencil[q][ki][wi][1];
     }
     dense.resize(Wb, 0.0);
-    shmem[0] = stencil_lds(nx, K, NL, Wb, sizeof(double));
-    shmem[1] = stencil_lds(nx, K, NL, Wb, sizeof(float));
+    shmem[0] = stencil_lds(nx, K, NL, Wb, sizeof(double), false);
+    shmem[1] = stencil_lds(nx, K, NL, Wb, sizeof(float), false);
+    shmem_io[0] = stencil_lds(nx, K, NL, Wb, sizeof(double), true);
+    shmem_io[1] = stencil_lds(nx, K, NL, Wb, sizeof(float), true);
     if (hipMalloc(&d_taps, dense.size() * sizeof(double)) != hipSuccess) return MGRIT_ENOMEM;
     bytes += dense.size() * sizeof(double);
     if (hipMemcpy(d_taps, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice) !=
@@ -136,12 +139,16 @@ int OpDesc::init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& 
             hipSuccess)
       return MGRIT_EHIP;
   }
-  for (int p = 0; p < 2; ++p)
-    for (KernelFn f : {fn[p], fn_io[p]})
-      if (f && shmem[p] > 64 * 1024 &&
-          hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)shmem[p]) != hipSuccess)
-        return MGRIT_EHIP;
+  for (int p = 0; p < 2; ++p) {
+    if (fn[p] && shmem[p] > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem[p]) != hipSuccess)
+      return MGRIT_EHIP;
+    if (fn_io[p] && shmem_io[p] > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)fn_io[p], hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem_io[p]) != hipSuccess)
+      return MGRIT_EHIP;
+  }
   return MGRIT_OK;
 }
 
@@ -242,8 +249,8 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
     e0 = take_event();
     (void)hipEventRecord(e0, stream);
   }
-  hipError_t st = hipLaunchKernel((const void*)fn, dim3(grid), dim3(op.NL), kargs,
-                                  op.shmem[prec], stream);
+  const size_t lds = (op.kind == OP_STENCIL && io) ? op.shmem_io[prec] : op.shmem[prec];
+  hipError_t st = hipLaunchKernel((const void*)fn, dim3(grid), dim3(op.NL), kargs, lds, stream);
   if (st != hipSuccess) return MGRIT_EHIP;
   if (profiling) {
     e1 = take_event();

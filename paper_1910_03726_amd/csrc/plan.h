@@ -21,6 +21,7 @@ struct OpDesc {
   KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
   KernelFn fn_io[2] = {nullptr, nullptr};  // stencil variants with per-step IO
   size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
+  size_t shmem_io[2] = {0, 0};          // the same for the per-step IO variants
   int NL = 0, K = 0;                    // lanes per workgroup, points per lane
   int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
   int ntaps = 0, nnz = 0;

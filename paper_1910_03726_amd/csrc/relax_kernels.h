@@ -31,6 +31,13 @@ __device__ __forceinline__ int wrap_hi(int i, int n) { return i >= n ? i - n : i
 __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Wait for every outstanding vector-memory load of this wavefront
+// (s_waitcnt vmcnt(0), other counters untouched).  Called once after values
+// that stay in registers through a step loop are loaded: without it the
+// wait for them is re-inserted at the loop head, where in every step it
+// also drains the prefetches and stores of the step before.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Deterministic block sum (fixed reduction order); result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -162,20 +169,22 @@ __device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K
 
 // IO = false: no per-step memory traffic (fine-level FC and residual
 // passes); IO = true: right-hand side every step and/or every state stored
-// (coarse levels, interpolation, sequential sweeps).  With IO the next
-// step's right-hand side row is requested one step before it is added.
+// (coarse levels, interpolation, sequential sweeps).
 //
 // Two ways to apply the stencil, chosen at compile time:
 //  * W-1 <= K (halo within the left neighbour lane): in place, right to
 //    left, halo values by cross-lane permute inside the wavefront and from a
 //    2*H-value LDS slot per wavefront across wavefronts;
 //  * W-1 > K (wide coarse operators): the chunk image of every lane sits in
-//    the staging area (padded layout), each output accumulates while halo
-//    values stream from LDS one at a time (registers ~2K instead of K+W).
-//    The same image feeds the per-step coalesced stores.
+//    LDS (padded layout), each output accumulates while halo values stream
+//    from LDS one at a time (registers ~2K instead of K+W).
 //
-// Dynamic LDS: the staging area (stage_doubles(n_x, K) doubles), followed
-// in the first case by 2*H slots per wavefront.
+// Dynamic LDS: staging area A (stage_doubles(n_x, K) doubles: start/end
+// rows and the chunk image), with IO a staging area B of the same size for
+// the right-hand side, then 2*H slots per wavefront (first case only).
+// With IO a step costs two barriers: the right-hand side of step s+1 is
+// written into B (and the row of step s+2 fetched into registers) while the
+// new chunk image goes into A.
 template <typename T, int K, int W, bool IO>
 __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   constexpr bool kShfl = (W - 1 <= K);
@@ -187,9 +196,12 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
   const int j = blockIdx.x;
   const int wave = lane >> 6, lw = lane & 63, nwave = NL >> 6;
+  const int nstage = stage_doubles(nx, K);
   const Stager<K> S{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
-  T* sm = reinterpret_cast<T*>(smem_raw + sizeof(double) * stage_doubles(nx, K));
+  double* rhs_stage = reinterpret_cast<double*>(smem_raw) + nstage;  // IO only
+  T* sm = reinterpret_cast<T*>(smem_raw + sizeof(double) * nstage * (IO ? 2 : 1));
   T* img = reinterpret_cast<T*>(S.stg);  // chunk image, padded layout, as T
+  const int b = lane * (K + 1);
 
   double v0[K];
   start_state<K>(a, j, S, v0);
@@ -205,20 +217,30 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   T tp[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) tp[t] = (T)a.taps[t];
+  wait_vmem();
 
   const bool every = IO && a.rhs_mode == RHS_EVERY;
   const bool store_steps = IO && a.mode == MODE_F;
   double gnext[IO ? K : 1];
+  // right-hand side row of step s into B at its frame shift (coalesced)
+  auto put_rhs = [&](int shift) {
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      rhs_stage[S.slot(S.local(lane + q * NL, shift))] = gnext[q];
+  };
+  __syncthreads();  // staging area A is free (start_state / stores done)
   if constexpr (IO) {
-    if (every && m >= 1) S.fetch(a.rhs + ((long long)j * m + 1) * nx, gnext);
+    if (every && m >= 1) {
+      S.fetch(a.rhs + ((long long)j * m + 1) * nx, gnext);
+      put_rhs(wrap_hi(a.omin, nx));
+      if (m >= 2) S.fetch(a.rhs + ((long long)j * m + 2) * nx, gnext);
+    }
   }
-  const int b = lane * (K + 1);
   if constexpr (!kShfl) {
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < K; ++k) img[b + k] = x[k];
-    __syncthreads();
   }
+  __syncthreads();
 
   int sh = 0;
   for (int s = 1; s <= m; ++s) {
@@ -284,20 +306,20 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
     sh = wrap_hi(sh + a.omin, nx);
     if constexpr (IO) {
       if (every) {
-        T g[K];
-        S.deliver(gnext, sh, g);
-        if (s < m) S.fetch(a.rhs + ((long long)j * m + s + 1) * nx, gnext);
 #pragma unroll
-        for (int k = 0; k < K; ++k) x[k] += g[k];
+        for (int k = 0; k < K; ++k) x[k] += (T)rhs_stage[b + k];
       }
-    }
-    if constexpr (!kShfl) {
-      // new image: the next step's halo source and the coalesced store
-      __syncthreads();
+      if (every || store_steps || !kShfl) {
+        __syncthreads();  // image and right-hand side of this step consumed
+        if (!kShfl || store_steps) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) img[b + k] = x[k];
-      __syncthreads();
-      if constexpr (IO) {
+          for (int k = 0; k < K; ++k) img[b + k] = x[k];
+        }
+        if (every && s < m) {
+          put_rhs(wrap_hi(sh + a.omin, nx));
+          if (s + 1 < m) S.fetch(a.rhs + ((long long)j * m + s + 2) * nx, gnext);
+        }
+        __syncthreads();
         if (store_steps && (s < m || a.write_last)) {
           double* row = a.out + ((long long)j * m + s) * nx;
 #pragma unroll
@@ -307,9 +329,11 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
           }
         }
       }
-    } else if constexpr (IO) {
-      if (store_steps && (s < m || a.write_last))
-        S.store(a.out + ((long long)j * m + s) * nx, sh, x);
+    } else if constexpr (!kShfl) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < K; ++k) img[b + k] = x[k];
+      __syncthreads();
     }
   }
   finish<T, K>(a, j, S, sh, x, red);

@@ -39,7 +39,7 @@ struct Req {
   enum { SETUP, READY, RUNNING, DONE } state = SETUP;
   int bypassed = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
-  mgrit_result res = {};
+  mgrit_result res = {0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0, 0, -1};
   std::vector<double> ufinal;
 };
 
@@ -51,31 +51,37 @@ struct Server {
   std::map<long long, std::shared_ptr<Req>> reqs;
   std::deque<std::shared_ptr<Req>> setup_q, ready_q, run_q;
   std::map<PsiKey, std::vector<Taps>> psi_cache;
-  long long next_id = 1, submitted = 0, completed = 0, hits = 0, misses = 0;
+  long long next_id = 1, submitted = 0, completed = 0, admitted = 0, hits = 0, misses = 0;
   size_t budget = 0, in_use = 0, peak = 0;
   int free_slots = 0, max_bypass = 0, device = 0;
   bool stopping = false;
   std::vector<std::thread> workers;
 
-  // Admit ready requests in submission order while slots and budget allow;
-  // a request that does not fit may be passed max_bypass times.  Caller
-  // holds `mu`.
+  // Admit ready requests in submission order while slots and budget allow.
+  // A ready request that does not fit may be passed (a later one admitted
+  // before it) at most max_bypass times; then admission waits for it.
+  // Requests still in setup do not hold others back.  Caller holds `mu`.
   void try_admit() {
+    std::vector<Req*> blocked;
     for (auto it = ready_q.begin(); it != ready_q.end() && free_slots > 0;) {
       Req& q = **it;
       if (in_use + q.bytes <= budget) {
+        bool stop = false;
+        for (Req* bq : blocked) stop |= ++bq->bypassed >= max_bypass;
         in_use += q.bytes;
         if (in_use > peak) peak = in_use;
         --free_slots;
         q.state = Req::RUNNING;
         q.t_admit = now_ms();
+        q.res.admit_seq = admitted++;
         run_q.push_back(*it);
         it = ready_q.erase(it);
         cv.notify_all();
+        if (stop) break;
         continue;
       }
       if (q.bypassed >= max_bypass) break;  // nobody may pass it any more
-      ++q.bypassed;
+      blocked.push_back(&q);
       ++it;
     }
   }

@@ -66,7 +66,7 @@ class Result(ctypes.Structure):
                 ("iterations", ctypes.c_int), ("levels", ctypes.c_int),
                 ("final_residual", ctypes.c_double), ("queue_ms", ctypes.c_double),
                 ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
-                ("hbm_bytes", ctypes.c_size_t)]
+                ("hbm_bytes", ctypes.c_size_t), ("admit_seq", ctypes.c_longlong)]
 
 
 class ServerStats(ctypes.Structure):

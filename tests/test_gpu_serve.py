@@ -70,25 +70,42 @@ def test_results_match_the_oracle():
 
 
 def test_admission_respects_budget_and_bypass_limit():
-    small = [dict(q, nx=256, nt=1024) for q in _mix(12, seed=13)]
-    big = dict(small[0], nx=1024, nt=4096, m=4, precision="fp64")
-    b_big = M.estimate_bytes(1024, 4096, 4, 4) + 2 * 1024 * 8
-    budget = int(1.2 * b_big)
-    with M.Server(budget, slots=4, setup_threads=2, max_bypass=2) as S:
+    # the budget holds the big request or a few small ones, never both; one
+    # coarse-operator configuration per size, cached first, and one setup
+    # thread, so requests become ready in submission order and the bypass
+    # rule alone decides the order of admission
+    small = [dict(_mix(1, seed=13)[0], nx=1024, nt=4096, m=4, precision="fp64",
+                  init_seed=100 + k) for k in range(12)]
+    big = dict(small[0], nx=2048, nt=8192)
+    L_small, L_big = 5, 6   # coarsest level >= 8 points: 4096/4^4, 8192/4^5
+    b_small = M.estimate_bytes(1024, 4096, 4, L_small) + 2 * 1024 * 8
+    b_big = M.estimate_bytes(2048, 8192, 4, L_big) + 2 * 2048 * 8
+    budget = b_big + b_small // 2
+    assert 4 * b_small <= budget
+    with M.Server(budget, slots=4, setup_threads=1, max_bypass=2) as S:
+        for q in (small[0], big):
+            res, _ = S.wait(_submit(S, q), q["nx"])
+            assert res.status == M.OK
+            assert res.levels == (L_small if q is small[0] else L_big)
+            assert res.hbm_bytes <= (b_small if q is small[0] else b_big)
         first = [_submit(S, q) for q in small[:4]]
         ib = _submit(S, big)
         rest = [_submit(S, q) for q in small[4:]]
-        seen_peak = 0
         out = {}
         for i, q in zip(first + [ib] + rest, small[:4] + [big] + small[4:]):
             res, u = S.wait(i, q["nx"])
             assert res.status == M.OK
             out[i] = res
-            seen_peak = max(seen_peak, S.stats().hbm_peak)
-        assert S.stats().hbm_peak <= budget
-    t_admit = {i: r.latency_ms - r.run_ms for i, r in out.items()}
-    passed = [i for i in rest if t_admit[i] < t_admit[ib]]
+        st = S.stats()
+        assert st.hbm_peak <= budget
+        assert st.psi_cache_hits >= len(small) - 1
+    seq = {i: r.admit_seq for i, r in out.items()}
+    assert sorted(seq.values()) == list(range(2, 2 + len(out)))
+    assert all(seq[i] < seq[ib] for i in first)
+    passed = [i for i in rest if seq[i] < seq[ib]]
     assert len(passed) <= 2
+    # the requests that passed are the earliest ones, in submission order
+    assert passed == rest[:len(passed)]
 
 
 def test_request_larger_than_budget_is_refused():
