@@ -1,9 +1,10 @@
 // Structures shared by the host planner and the gfx950 kernels of libmgrit.
 //
 // Layout in HBM: every space-time array is row-major [time level][n_x] FP64.
-// A relaxation launch processes `nint` coarse intervals, one workgroup each
-// (the time-parallel dimension of MGRIT, Sec. 2.2); the spatial state of an
-// interval stays on-chip (registers or LDS) for all of its fine steps.
+// A relaxation launch processes `nint` coarse intervals (the time-parallel
+// dimension of MGRIT, Sec. 2.2), one workgroup per interval and spatial
+// tile; the spatial state of a tile stays on-chip (registers or LDS) for
+// all of its fine steps.
 #pragma once
 
 #include <stdint.h>
@@ -48,6 +49,12 @@ struct RelaxArgs {
   int write_row0;          // MODE_FC: block 0 also writes out[0] = start_0
   int out_off;             // MODE_FC: out row of interval j is j + out_off
   int write_last;          // MODE_F: also write the state after step m
+  int skip_row0;           // MODE_F: the start row is already stored (chunked sweeps)
+  int tile;                // stencil kernel: points per tile
+  int tiles;               // stencil kernel: tiles per interval (block b: tile
+                           // b % tiles of interval b / tiles)
+  int preload;             // stencil kernel, RHS_EVERY: all m right-hand side
+                           // rows staged in LDS before the first step
 };
 
 // One factor of a cyclic banded stage solve: a linear recurrence of order

@@ -10,8 +10,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mgrit.h"
@@ -24,53 +26,85 @@ namespace mgr {
 // ---------------------------------------------------------------------------
 // kernel selection
 // ---------------------------------------------------------------------------
-// LDS bytes of k_stencil for n_x, chunk K, NL lanes, compiled width Wb.
-static size_t stencil_lds(int nx, int K, int NL, int Wb, size_t el, bool io) {
-  const int H = std::min(Wb - 1, K);
-  const size_t stage = sizeof(double) * (size_t)(nx + nx / K);
-  return stage * (io ? 2 : 1) +
-         ((Wb - 1 <= K) ? 2 * (size_t)(NL / 64) * std::max(H, 1) * el : 0);
-}
-
-// Largest chunk K whose k_stencil<double,K,Wb,io> instantiation compiles
-// without register spills on gfx950 (from the compiler's resource usage
-// report: long chunks plus a wide window or a prefetched right-hand side
-// row exceed 256 VGPRs).
-static int max_spill_free_k(int Wb, bool io) {
-  if (!io) return Wb <= 32 ? 32 : 16;
-  if (Wb <= 24) return 16;
-  return 8;
-}
-
-static bool pick_stencil_shape(int nx, int Wb, bool seq, bool io, int& K, int& NL) {
-  // Lanes own K contiguous points, NL = nx/K lanes (a multiple of 64, at
-  // most 512).  Take the longest spill-free chunk (more independent FMAs per
-  // lane, halo amortized); the single-workgroup sequential sweep takes the
-  // most lanes (up to 512, two wavefronts per SIMD) within that bound.  If
-  // no spill-free shape has <= 512 lanes, take the shortest chunk that has.
-  // Every candidate must fit the CU's 160 KB of LDS.
-  const int kmax = max_spill_free_k(Wb, io);
-  int bestK = -1, fallbackK = -1;
-  for (int i = 0; i < kNumK; ++i) {
-    const int k = kKs[i];
-    if (nx % k) continue;
-    const int nl = nx / k;
-    if (nl % 64 || nl > 512 || nl < 64) continue;
-    if (Wb - 1 > nx) continue;
-    if (stencil_lds(nx, k, nl, Wb, sizeof(double), true) > 160 * 1024) continue;
-    if (fallbackK < 0) fallbackK = k;  // kKs ascends: the shortest valid chunk
-    if (k > kmax) continue;
-    if (seq) {
-      if (bestK < 0) bestK = k;        // most lanes
-    } else {
-      bestK = k;                       // longest chunk
-    }
+// LDS bytes of k_stencil for an extent of E points, chunk K, NL lanes,
+// compiled width Wb and state element size el.
+static size_t stencil_lds(int E, int K, int NL, int Wb, size_t el) {
+  const size_t stage = sizeof(double) * (size_t)(E + E / K);
+  if (Wb - 1 <= K) {
+    const int H = std::min(Wb - 1, K);
+    return stage + 2 * (size_t)(NL / 64) * std::max(H, 1) * el;
   }
-  if (bestK < 0) bestK = fallbackK;
-  if (bestK < 0) return false;
-  K = bestK;
-  NL = nx / K;
-  return true;
+  const int M = (Wb - 1 + K - 1) / K * K;
+  const size_t img = (size_t)((E + M) + (E + M) / K) * el;
+  return std::max(stage, 2 * img);
+}
+
+// Per-kernel facts from its code object, cached: whether it spills
+// registers to scratch memory, and the dynamic LDS it may use, which is
+// raised once to all of the CU's 160 KB not taken by static LDS (a limit,
+// not a reservation; never lowered, so plans of any size can share it).
+struct KernelInfo {
+  bool spills = true;
+  size_t max_lds = 0;
+};
+
+static KernelInfo kernel_info(KernelFn fn) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, KernelInfo> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find((const void*)fn);
+  if (it != cache.end()) return it->second;
+  KernelInfo ki;
+  hipFuncAttributes attr;
+  std::memset(&attr, 0, sizeof attr);
+  if (hipFuncGetAttributes(&attr, (const void*)fn) == hipSuccess) {
+    ki.spills = attr.localSizeBytes > 0;
+    const size_t want = 160 * 1024 - std::min<size_t>(attr.sharedSizeBytes, 160 * 1024);
+    if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)want) == hipSuccess) {
+      ki.max_lds = want;
+    } else {
+      (void)hipGetLastError();
+      ki.max_lds = 64 * 1024;
+    }
+  } else {
+    (void)hipGetLastError();
+  }
+  cache[(const void*)fn] = ki;
+  return ki;
+}
+
+static bool spills(KernelFn fn) { return kernel_info(fn).spills; }
+
+// Launch-time model of one stencil pass on the 256 CUs of the chip (2.4
+// GHz): nwg workgroups of NL lanes x K points, S steps of Wb taps.  A step
+// of the `conc` workgroups resident on a CU costs the larger of a latency
+// floor (LDS round trips, barriers, dependent FMAs: about 1.1 us measured
+// for every shape) and 1.8x its FMA issue time (16 FP64/FP32 lanes per
+// SIMD per clock, 4 SIMDs; the factor covers LDS and address work); each
+// round of resident workgroups adds its start/end row traffic, each launch
+// a fixed cost.  Fitted to launch-shape sweeps on MI355X.
+static double stencil_time_us(int nwg, int NL, int K, int Wb, int S, int occ) {
+  const int kCU = 256;
+  const double clk_us = 1.0 / 2400.0;
+  occ = std::max(occ, 1);
+  const int conc = std::min(occ, (nwg + kCU - 1) / kCU);
+  const int nw = NL / 64;
+  const double fma = std::ceil(conc * nw / 4.0) * K * Wb * 4.0;
+  const double step = std::max(2700.0, 1.8 * fma);
+  const long long rounds = (nwg + (long long)kCU * occ - 1) / ((long long)kCU * occ);
+  return rounds * (S * step + 4000.0) * clk_us + 2.0;
+}
+
+static int occupancy(KernelFn fn, int NL, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, NL, lds) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  if (nb < 1) nb = 1;
+  return nb;
 }
 
 static int pick_width(int W) {
@@ -79,76 +113,182 @@ static int pick_width(int W) {
   return -1;
 }
 
-int OpDesc::init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& err) {
+// Fill the kernels and LDS sizes of shape `sh` (K, NL set); false if it
+// does not fit the CU's 160 KB of LDS.
+static bool finish_shape(StencilShape& sh, int E, int Wb, bool io) {
   const KernelTable& kt = kernel_table();
+  const int ki = k_index(sh.K), wi = width_index(Wb);
+  if (ki < 0 || wi < 0) return false;
+  sh.shmem[0] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(double));
+  sh.shmem[1] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(float));
+  if (sh.shmem[0] > 160 * 1024) return false;
+  for (int q = 0; q < 2; ++q) {
+    sh.fn[q] = kt.stencil[q][ki][wi][io ? 1 : 0];
+    if (!sh.fn[q]) return false;
+  }
+  return true;
+}
+
+// Right-hand side rows a pass may stage in LDS next to the shape's own
+// LDS: up to the kernel's LDS limit when the launch has at most two
+// workgroups per CU anyway, else within 64 KB (keeps two or more
+// resident).  False if the shape itself does not fit.
+static bool set_lds(StencilShape& sh, long long nwg, bool io) {
+  const size_t lim = std::min(kernel_info(sh.fn[0]).max_lds, kernel_info(sh.fn[1]).max_lds);
+  if (sh.shmem[0] > lim) return false;
+  const size_t row = sizeof(double) * (size_t)sh.NL * (sh.K + 1);
+  const size_t budget = nwg <= 2 * 256 ? lim : std::min<size_t>(lim, 64 * 1024);
+  sh.preload_rows = (io && sh.shmem[0] < budget) ? (int)((budget - sh.shmem[0]) / row) : 0;
+  return true;
+}
+
+// Untiled shape: NL = n_x/K lanes (a multiple of 64, at most 512) over the
+// whole periodic line, the spill-free chunk with the lowest modelled time
+// for S steps over nblk workgroups (if none is spill-free, the fastest
+// modelled one).
+static bool pick_whole(int nx, int Wb, int S, int nblk, bool io, StencilShape& out) {
+  bool found = false, spill_free = false;
+  for (int i = 0; i < kNumK; ++i) {
+    StencilShape sh;
+    sh.K = kKs[i];
+    if (nx % sh.K) continue;
+    sh.NL = nx / sh.K;
+    if (sh.NL % 64 || sh.NL > 512 || sh.NL < 64 || Wb - 1 > nx) continue;
+    if (!finish_shape(sh, nx, Wb, io)) continue;
+    const bool sf = !spills(sh.fn[0]) && !spills(sh.fn[1]);
+    if (found && spill_free && !sf) continue;
+    sh.tiles = 1;
+    sh.tile = nx;
+    sh.max_steps = 1 << 30;
+    if (!set_lds(sh, nblk, io)) continue;
+    sh.est_us = stencil_time_us(nblk, sh.NL, sh.K, Wb, S, occupancy(sh.fn[0], sh.NL, sh.shmem[0]));
+    if (!found || (sf && !spill_free) || sh.est_us < out.est_us) {
+      out = sh;
+      found = true;
+      spill_free = sf;
+    }
+  }
+  return found;
+}
+
+// Tiled shape for passes of S steps of a window of true width `width`:
+// extent E = NL*K < n_x, tile C = E - S*(width-1) outputs, ceil(n_x/C)
+// tiles; the spill-free shape with the lowest modelled time.
+static bool pick_tiled(int nx, int width, int Wb, int S, int nblk, bool io, int max_tiles,
+                       StencilShape& out) {
+  const long long G = (long long)S * (width - 1);
+  bool found = false;
+  for (int i = 0; i < kNumK; ++i) {
+    const int K = kKs[i];
+    for (int NL = 64; NL <= 512; NL += 64) {
+      const long long E = (long long)NL * K;
+      if (E >= nx || E <= G) continue;
+      StencilShape sh;
+      sh.K = K;
+      sh.NL = NL;
+      sh.tile = (int)(E - G);
+      sh.tiles = (nx + sh.tile - 1) / sh.tile;
+      sh.max_steps = S;
+      if (sh.tiles < 2 || sh.tiles > max_tiles) continue;
+      if (!finish_shape(sh, (int)E, Wb, io) || spills(sh.fn[0]) || spills(sh.fn[1])) continue;
+      if (!set_lds(sh, (long long)nblk * sh.tiles, io)) continue;
+      sh.est_us = stencil_time_us((int)std::min<long long>((long long)nblk * sh.tiles, 1 << 30),
+                                  NL, K, Wb, S, occupancy(sh.fn[0], NL, sh.shmem[0]));
+      if (!found || sh.est_us < out.est_us) {
+        out = sh;
+        found = true;
+      }
+    }
+  }
+  return found;
+}
+
+int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, int max_tiles,
+                         std::string& err) {
   nnz = (int)t.off.size();
   std::vector<double> dense;
   int W = 1;
   tap_window(t, nx, omin, W, dense);
   width = W;
   const int Wb = pick_width(W);
-  int k = 0, nl = 0;
-  if (Wb > 0 && pick_stencil_shape(nx, Wb, seq, io, k, nl)) {
-    kind = OP_STENCIL;
-    K = k;
-    NL = nl;
-    Wbucket = Wb;
-    const int ki = k_index(K), wi = width_index(Wb);
-    for (int q = 0; q < 2; ++q) {
-      fn[q] = kt.stencil[q][ki][wi][0];
-      fn_io[q] = kt.stencil[q][ki][wi][1];
+  bool ok = Wb > 0;
+  if (ok && seq) {
+    // sequential sweep: steps per launch and shape with the lowest modelled
+    // total time (launches run back to back on one stream)
+    double best = 1e300;
+    ok = pick_whole(nx, Wb, steps, 1, true, whole[1]) && pick_whole(nx, Wb, steps, 1, false, whole[0]);
+    if (ok) {
+      best = (spills(whole[1].fn[0]) || spills(whole[1].fn[1])) ? 1e300 : whole[1].est_us;
+      seq_chunk = steps;
+      for (int S = 4; S < steps; S *= 2) {
+        StencilShape sh;
+        if (!pick_tiled(nx, W, Wb, S, 1, true, max_tiles, sh)) continue;
+        const double tot = ((steps + S - 1) / S) * sh.est_us;
+        if (tot < best) {
+          best = tot;
+          seq_chunk = S;
+          tiled[1] = sh;
+        }
+      }
     }
+  } else if (ok) {
+    for (int io = 0; io < 2 && ok; ++io) {
+      ok = pick_whole(nx, Wb, steps, nblk, io, whole[io]);
+      StencilShape sh;
+      const bool whole_spills = ok && (spills(whole[io].fn[0]) || spills(whole[io].fn[1]));
+      if (ok && steps >= 1 && pick_tiled(nx, W, Wb, steps, nblk, io, max_tiles, sh) &&
+          (whole_spills || sh.est_us < whole[io].est_us))
+        tiled[io] = sh;
+    }
+  }
+  if (ok) {
+    kind = OP_STENCIL;
+    K = whole[0].K;
+    NL = whole[0].NL;
+    Wbucket = Wb;
     dense.resize(Wb, 0.0);
-    shmem[0] = stencil_lds(nx, K, NL, Wb, sizeof(double), false);
-    shmem[1] = stencil_lds(nx, K, NL, Wb, sizeof(float), false);
-    shmem_io[0] = stencil_lds(nx, K, NL, Wb, sizeof(double), true);
-    shmem_io[1] = stencil_lds(nx, K, NL, Wb, sizeof(float), true);
     if (hipMalloc(&d_taps, dense.size() * sizeof(double)) != hipSuccess) return MGRIT_ENOMEM;
     bytes += dense.size() * sizeof(double);
     if (hipMemcpy(d_taps, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice) !=
         hipSuccess)
       return MGRIT_EHIP;
-  } else {
-    // generic LDS kernel: state of 2 n_x values in LDS
-    if ((size_t)2 * nx * sizeof(double) > 160 * 1024) {
+    return MGRIT_OK;
+  }
+  // generic LDS kernel: state of 2 n_x values in LDS
+  if ((size_t)2 * nx * sizeof(double) > 160 * 1024) {
+    err = "n_x too large for the generic relaxation kernel";
+    return MGRIT_EINVAL;
+  }
+  const KernelTable& kt = kernel_table();
+  kind = OP_GENERIC;
+  NL = 256;
+  fn[0] = kt.generic[0];
+  fn[1] = kt.generic[1];
+  shmem[0] = (size_t)2 * nx * sizeof(double);
+  shmem[1] = (size_t)2 * nx * sizeof(float);
+  std::vector<int> off;
+  std::vector<double> w;
+  for (int q = 0; q < W; ++q)
+    if (dense[q] != 0.0) {
+      off.push_back((omin + q) % nx);
+      w.push_back(dense[q]);
+    }
+  ntaps = (int)off.size();
+  omin = 0;
+  if (hipMalloc(&d_taps, std::max<size_t>(1, w.size()) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&d_off, std::max<size_t>(1, off.size()) * sizeof(int)) != hipSuccess)
+    return MGRIT_ENOMEM;
+  bytes += w.size() * (sizeof(double) + sizeof(int));
+  if (hipMemcpy(d_taps, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return MGRIT_EHIP;
+  for (int p = 0; p < 2; ++p)
+    if (shmem[p] > kernel_info(fn[p]).max_lds) {
       err = "n_x too large for the generic relaxation kernel";
       return MGRIT_EINVAL;
     }
-    kind = OP_GENERIC;
-    NL = 256;
-    fn[0] = kt.generic[0];
-    fn[1] = kt.generic[1];
-    shmem[0] = (size_t)2 * nx * sizeof(double);
-    shmem[1] = (size_t)2 * nx * sizeof(float);
-    std::vector<int> off;
-    std::vector<double> w;
-    for (int q = 0; q < W; ++q)
-      if (dense[q] != 0.0) {
-        off.push_back((omin + q) % nx);
-        w.push_back(dense[q]);
-      }
-    ntaps = (int)off.size();
-    omin = 0;
-    if (hipMalloc(&d_taps, std::max<size_t>(1, w.size()) * sizeof(double)) != hipSuccess ||
-        hipMalloc(&d_off, std::max<size_t>(1, off.size()) * sizeof(int)) != hipSuccess)
-      return MGRIT_ENOMEM;
-    bytes += w.size() * (sizeof(double) + sizeof(int));
-    if (hipMemcpy(d_taps, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) !=
-            hipSuccess)
-      return MGRIT_EHIP;
-  }
-  for (int p = 0; p < 2; ++p) {
-    if (fn[p] && shmem[p] > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shmem[p]) != hipSuccess)
-      return MGRIT_EHIP;
-    if (fn_io[p] && shmem_io[p] > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)fn_io[p], hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shmem_io[p]) != hipSuccess)
-      return MGRIT_EHIP;
-  }
   return MGRIT_OK;
 }
 
@@ -187,10 +327,10 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
   nnz = 0;
   for (int p = 0; p < 2; ++p)
-    if (shmem[p] > 64 * 1024 &&
-        hipFuncSetAttribute((const void*)fn[p], hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)shmem[p]) != hipSuccess)
-      return MGRIT_EHIP;
+    if (shmem[p] > kernel_info(fn[p]).max_lds) {
+      err = "n_x too large for the SDIRK kernel's LDS staging";
+      return MGRIT_EINVAL;
+    }
   if (hipMalloc(&d_sdirk, sizeof(SdirkDev)) != hipSuccess) return MGRIT_ENOMEM;
   bytes += sizeof(SdirkDev);
   if (hipMemcpy(d_sdirk, &sd, sizeof(SdirkDev), hipMemcpyHostToDevice) != hipSuccess)
@@ -209,9 +349,20 @@ void OpDesc::release() {
 
 std::string OpDesc::describe() const {
   char buf[160];
-  if (kind == OP_STENCIL)
+  if (kind == OP_STENCIL) {
+    std::string d;
     snprintf(buf, sizeof buf, "stencil<K=%d,W=%d(of %d)> NL=%d omin=%d nnz=%d", K, Wbucket,
              width, NL, omin, nnz);
+    d = buf;
+    for (int io = 0; io < 2; ++io)
+      if (tiled[io].tiles > 1) {
+        snprintf(buf, sizeof buf, " %s:%dx%d<K=%d>NL=%d/%d steps", io ? "io" : "plain",
+                 tiled[io].tiles, tiled[io].tile, tiled[io].K, tiled[io].NL,
+                 tiled[io].max_steps);
+        d += buf;
+      }
+    return d;
+  }
   else if (kind == OP_GENERIC)
     snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
   else
@@ -233,6 +384,8 @@ static RelaxArgs base_args(const Plan& P, const OpDesc& op) {
   a.nx = P.nx;
   a.in_stride = 1;
   a.corr_stride = 1;
+  a.tile = P.nx;
+  a.tiles = 1;
   return a;
 }
 
@@ -240,17 +393,38 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
   // stencil kernels come without per-step memory traffic unless the pass
   // adds a right-hand side every step or stores every state
   const bool io = a.rhs_mode == RHS_EVERY || a.mode == MODE_F;
-  KernelFn fn = (op.kind == OP_STENCIL && io) ? op.fn_io[prec] : op.fn[prec];
-  if (!fn) return MGRIT_EINVAL;
   RelaxArgs args = a;
+  KernelFn fn = op.fn[prec];
+  int nl = op.NL;
+  size_t lds = op.shmem[prec];
+  long long blocks = grid;
+  parts = grid;
+  if (op.kind == OP_STENCIL) {
+    const StencilShape* sh = &op.whole[io];
+    if (op.tiled[io].tiles > 1 && a.m >= 1 && a.m <= op.tiled[io].max_steps)
+      sh = &op.tiled[io];
+    fn = sh->fn[prec];
+    nl = sh->NL;
+    lds = sh->shmem[prec];
+    args.tile = sh->tile;
+    args.tiles = sh->tiles;
+    args.preload = 0;
+    if (io && a.rhs_mode == RHS_EVERY && a.m >= 1 && a.m <= sh->preload_rows) {
+      args.preload = 1;
+      lds += sizeof(double) * (size_t)a.m * sh->NL * (sh->K + 1);
+    }
+    blocks = (long long)grid * sh->tiles;
+    parts = (int)blocks;
+  }
+  if (!fn || blocks < 1 || blocks > 0x7fffffffLL) return MGRIT_EINVAL;
   void* kargs[] = {&args};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (profiling) {
     e0 = take_event();
     (void)hipEventRecord(e0, stream);
   }
-  const size_t lds = (op.kind == OP_STENCIL && io) ? op.shmem_io[prec] : op.shmem[prec];
-  hipError_t st = hipLaunchKernel((const void*)fn, dim3(grid), dim3(op.NL), kargs, lds, stream);
+  hipError_t st =
+      hipLaunchKernel((const void*)fn, dim3((unsigned)blocks), dim3(nl), kargs, lds, stream);
   if (st != hipSuccess) return MGRIT_EHIP;
   if (profiling) {
     e1 = take_event();
@@ -350,19 +524,31 @@ int Plan::copy_cpoints(int l, int prec, const double* in, long long in_stride,
 
 // Coarsest level: x^0 = g^0 = 0, x^{n+1} = Phi_L x^n + g^{n+1}, all points.
 // Always FP64 (the sequential coarse solve stays FP64 in every precision).
+// The sweep runs in launches of op.seq_chunk steps, each starting from the
+// last row the one before stored.
 int Plan::sequential(const double* g) {
   Level& L = lev.back();
   const OpDesc& op = L.seq;
-  RelaxArgs a = base_args(*this, op);
-  a.zero_in = 1;
-  a.rhs = g;
-  a.rhs_mode = RHS_EVERY;
-  a.mode = MODE_F;
-  a.m = L.n;
-  a.nint = 1;
-  a.write_last = 1;
-  a.out = L.X;
-  return launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
+  const int S = op.seq_chunk > 0 ? op.seq_chunk : L.n;
+  for (int s0 = 0; s0 < L.n; s0 += S) {
+    RelaxArgs a = base_args(*this, op);
+    if (s0 == 0) {
+      a.zero_in = 1;
+    } else {
+      a.in = L.X + (long long)s0 * nx;
+      a.skip_row0 = 1;
+    }
+    a.rhs = g + (long long)s0 * nx;
+    a.rhs_mode = RHS_EVERY;
+    a.mode = MODE_F;
+    a.m = std::min(S, L.n - s0);
+    a.nint = 1;
+    a.write_last = 1;
+    a.out = L.X + (long long)s0 * nx;
+    const int rc = launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
+    if (rc) return rc;
+  }
+  return MGRIT_OK;
 }
 
 int Plan::norm(const double* partial, int n, double& value) {
@@ -422,7 +608,7 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
     b += (size_t)(n + 1) * row;                                 // X_l
     if (l < levels - 1) b += 2 * (size_t)(n / m + 1) * row;     // V_l, R_l
   }
-  b += (size_t)(nc + 2) * sizeof(double);                       // partials, norm
+  b += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);  // partials, norm
   return b;
 }
 }  // namespace mgr
@@ -571,14 +757,14 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
         else {
           Taps f;
           erk_taps(t, cfl, nx, f);
-          rc = L.op.init_stencil(f, nx, false, false, err);
+          rc = L.op.init_stencil(f, nx, m, (int)(n / m), false, kMaxFineTiles, err);
         }
       } else {
         Taps f;
         f.off.assign(psi[l - 1].offset, psi[l - 1].offset + psi[l - 1].nnz);
         f.w.assign(psi[l - 1].weight, psi[l - 1].weight + psi[l - 1].nnz);
-        if (l < levels - 1) rc = L.op.init_stencil(f, nx, false, true, err);
-        else rc = L.seq.init_stencil(f, nx, true, true, err);
+        if (l < levels - 1) rc = L.op.init_stencil(f, nx, m, (int)(n / m), false, 1 << 20, err);
+        else rc = L.seq.init_stencil(f, nx, (int)n, 1, true, 1 << 20, err);
       }
       if (rc) return fail(rc);
       P->bytes += L.op.bytes + L.seq.bytes;
@@ -602,11 +788,12 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
       if (l < levels - 1 && (!alloc(&L.V, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
         return fail(MGRIT_ENOMEM);
     }
-    if (hipMalloc((void**)&P->partial, (size_t)(nc + 1) * sizeof(double)) != hipSuccess ||
+    if (hipMalloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double)) !=
+            hipSuccess ||
         hipMalloc((void**)&P->d_norm, sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&P->h_norm, sizeof(double)) != hipSuccess)
       return fail(MGRIT_ENOMEM);
-    P->bytes += (size_t)(nc + 2) * sizeof(double);
+    P->bytes += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);
     std::string d;
     for (int l = 0; l < levels; ++l) {
       const OpDesc& o = (l == levels - 1) ? P->lev[l].seq : P->lev[l].op;
@@ -794,7 +981,7 @@ static int solve_fp64(Plan* P, const double* u0, const double* uinit, double tol
       return rc;
     P->stats.fine_passes_fp64 += 1;
     double res = 0.0;
-    if ((rc = P->norm(P->partial, nc, res))) return rc;
+    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
     if (hist) hist[it] = res;
     P->stats.final_residual = res;
     if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
@@ -831,7 +1018,7 @@ static int solve_ir(Plan* P, const double* u0, const double* uinit, double tol, 
       return rc;
     P->stats.fine_passes_fp64 += 1;
     double res = 0.0;
-    if ((rc = P->norm(P->partial, nc, res))) return rc;
+    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
     if (hist) hist[outer] = res;
     P->stats.final_residual = res;
     if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
@@ -855,7 +1042,7 @@ static int solve_ir(Plan* P, const double* u0, const double* uinit, double tol, 
         return rc;
       P->stats.fine_passes_fp32 += 1;
       double rho = 0.0;
-      if ((rc = P->norm(P->partial, nc, rho))) return rc;
+      if ((rc = P->norm(P->partial, P->parts, rho))) return rc;
       if (!std::isfinite(rho)) { status = MGRIT_EDIVERGED; break; }
       // stop at the target, at the cap, or once a coarse correction stops
       // halving the inner residual (FP32 rounding floor)

@@ -15,13 +15,29 @@ namespace mgr {
 
 enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
 
+// Fine-level residual passes write one partial sum per interval and tile.
+constexpr int kMaxFineTiles = 16;
+
+// One launch shape of the stencil kernel: `tiles` workgroups per interval,
+// each of NL lanes x K points, writing `tile` points.  A tiled shape
+// (tiles > 1) is valid for passes of at most `max_steps` steps (the tile's
+// dependence cone must fit its extent); the untiled one for any count.
+struct StencilShape {
+  int K = 0, NL = 0, tiles = 1, tile = 0, max_steps = 0;
+  int preload_rows = 0;                 // passes of <= this many steps stage
+                                        // their right-hand side rows in LDS
+  KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
+  size_t shmem[2] = {0, 0};
+  double est_us = 0.0;                  // planner's launch-time estimate
+};
+
 // The relaxation operator of one level and the kernels that apply it.
 struct OpDesc {
   int kind = OP_GENERIC;
-  KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
-  KernelFn fn_io[2] = {nullptr, nullptr};  // stencil variants with per-step IO
+  KernelFn fn[2] = {nullptr, nullptr};  // generic / SDIRK: [FP64 state, FP32 state]
   size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
-  size_t shmem_io[2] = {0, 0};          // the same for the per-step IO variants
+  StencilShape whole[2], tiled[2];      // stencil: [no per-step IO, per-step IO]
+  int seq_chunk = 0;                    // sequential sweeps: steps per launch
   int NL = 0, K = 0;                    // lanes per workgroup, points per lane
   int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
   int ntaps = 0, nnz = 0;
@@ -30,7 +46,11 @@ struct OpDesc {
   void* d_sdirk = nullptr;
   size_t bytes = 0;
 
-  int init_stencil(const Taps& t, int nx, bool seq, bool io, std::string& err);
+  // steps: fine steps of one relaxation pass (m), or of the whole sweep
+  // (seq); nblk: workgroup rows of a pass (intervals); max_tiles: bound on
+  // tiles per interval
+  int init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, int max_tiles,
+                   std::string& err);
   int init_sdirk(const Tableau& t, double cfl, int nx, std::string& err);
   void release();
   std::string describe() const;
@@ -70,6 +90,7 @@ struct Plan {
   double fine_dof_steps = 0.0, prof_dof_base = 0.0;
   std::vector<ProfPending> pending;
   std::vector<hipEvent_t> event_pool;
+  int parts = 0;  // partial sums written by the last residual launch
 
   int launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int cls);
   hipEvent_t take_event();

@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace mgr {
@@ -167,9 +169,106 @@ __device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K
   }
 }
 
+// Extent of a stencil workgroup: E = NL*K consecutive frame positions e
+// (lane l owns e = l*K .. l*K+K-1).  Position e of a row whose frame shift
+// is sh is the true point (f0 + e + sh) mod n_x.  Rows are staged through
+// LDS with slot(e) = e + e/K: the coalesced order (e = lane + q*NL) and the
+// chunk order are both free of bank conflicts.
+template <int K>
+struct Extent {
+  int nx, NL, lane, E, f0;  // f0 in [0, n_x), E <= 2 n_x
+  __device__ __forceinline__ static int slot(int e) { return e + e / K; }
+  // true point of position 0 at frame shift sh (sh in [0, n_x))
+  __device__ __forceinline__ int first(int sh) const { return wrap_hi(f0 + sh, nx); }
+  __device__ __forceinline__ int at(int b, int e) const {
+    int g = b + e;
+    g -= (g >= nx) ? nx : 0;
+    g -= (g >= nx) ? nx : 0;
+    return g;
+  }
+  // global -> registers, coalesced (element q is position lane + q*NL)
+  __device__ __forceinline__ void fetch(const double* row, int sh, double (&r)[K]) const {
+    const int b = first(sh);
+#pragma unroll
+    for (int q = 0; q < K; ++q) r[q] = row[at(b, lane + q * NL)];
+  }
+  __device__ __forceinline__ void put(double* stg, const double (&r)[K]) const {
+#pragma unroll
+    for (int q = 0; q < K; ++q) stg[slot(lane + q * NL)] = r[q];
+  }
+  // this lane's chunk of a row, straight from global memory
+  __device__ __forceinline__ void chunk(const double* row, int sh, double (&r)[K]) const {
+    const int b = first(sh);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = row[at(b, lane * K + k)];
+  }
+};
+
+// Stores after the last step of a stencil workgroup (MODE_FC / MODE_RES):
+// the tile's positions [eout, E) of the state x (frame shift sh), staged
+// for coalesced access; residuals and their partial sum (one per
+// workgroup, at partial[j * tiles + c], i.e. at its block index).
+template <typename T, int K>
+__device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const Extent<K>& X, int eout, int sh,
+                                              const T (&x)[K], double* stg, double* red) {
+  if (a.mode != MODE_FC && a.mode != MODE_RES) return;
+  const int nx = a.nx, NL = X.NL, lane = X.lane, E = X.E;
+  __syncthreads();  // the image / staging area is no longer read
+  const int b = lane * (K + 1);
+#pragma unroll
+  for (int k = 0; k < K; ++k) stg[b + k] = (double)x[k];
+  __syncthreads();
+  const int bs = X.first(sh);
+  const long long rj = (long long)(j + 1) * nx;
+  double ss = 0.0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int e = eout + lane + q * NL;
+    if (e < E) {
+      const int g = X.at(bs, e);
+      double v = stg[Extent<K>::slot(e)];
+      if (a.rhs_mode == RHS_CPOINT) v += a.rhs[rj + g];
+      if (a.mode == MODE_FC) {
+        a.out[(long long)(j + a.out_off) * nx + g] = v;
+      } else {
+        v -= a.ref[rj + g];
+        a.out[rj + g] = v;
+        ss += v * v;
+      }
+    }
+  }
+  if (a.mode == MODE_RES) {
+    if (j == 0) {  // r^0 = 0 over this tile
+      const int b0 = X.first(0);
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const int e = eout + lane + q * NL;
+        if (e < E) a.out[X.at(b0, e)] = 0.0;
+      }
+    }
+    if (a.partial) {
+      const double s = block_sum(ss, red);
+      if (lane == 0) a.partial[blockIdx.x] = s;
+    }
+  }
+}
+
+// The stencil kernel.  Workgroup (c, j) -- block j*tiles + c of a 1-D grid
+// -- advances interval j by m steps of
+// a periodic window-W stencil (the ERK stepper of Corollary 1 or a coarse
+// operator Psi) and writes the points of tile c: true frame positions
+// [c*C, min((c+1)*C, n_x)) with C = a.tile.  With one tile (C = E = n_x)
+// the extent is the whole periodic line.  With several tiles the extent
+// ends at the tile's end and reaches m*(W-1) points upwind of it, the
+// dependence cone of the tile over m steps: the points left of the cone
+// are computed from wrapped neighbours and discarded (redundant work
+// bought for parallelism across CUs without any inter-workgroup sync).
+//
 // IO = false: no per-step memory traffic (fine-level FC and residual
-// passes); IO = true: right-hand side every step and/or every state stored
-// (coarse levels, interpolation, sequential sweeps).
+// passes); IO = true: a right-hand side row every step and/or every state
+// stored (coarse levels, interpolation, sequential sweeps).  Per-step rows
+// move between HBM and each lane's chunk directly; right-hand side rows are
+// prefetched two steps ahead.
 //
 // Two ways to apply the stencil, chosen at compile time:
 //  * W-1 <= K (halo within the left neighbour lane): in place, right to
@@ -179,12 +278,11 @@ __device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K
 //    LDS (padded layout), each output accumulates while halo values stream
 //    from LDS one at a time (registers ~2K instead of K+W).
 //
-// Dynamic LDS: staging area A (stage_doubles(n_x, K) doubles: start/end
-// rows and the chunk image), with IO a staging area B of the same size for
-// the right-hand side, then 2*H slots per wavefront (first case only).
-// With IO a step costs two barriers: the right-hand side of step s+1 is
-// written into B (and the row of step s+2 fetched into registers) while the
-// new chunk image goes into A.
+// Dynamic LDS: with `preload` first the m right-hand side rows (staged
+// layout, E + E/K doubles each), then the staging area (E + E/K doubles:
+// start/end rows), which in the second case also holds the two chunk images (2*((E+M) + (E+M)/K)
+// values of T, M = W-1 rounded up to a multiple of K), then 2*H slots per
+// wavefront (first case only).
 template <typename T, int K, int W, bool IO>
 __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   constexpr bool kShfl = (W - 1 <= K);
@@ -194,26 +292,73 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   __shared__ double red[16];
 
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
-  const int j = blockIdx.x;
+  const int c = (int)(blockIdx.x % (unsigned)a.tiles), j = (int)(blockIdx.x / (unsigned)a.tiles);
   const int wave = lane >> 6, lw = lane & 63, nwave = NL >> 6;
-  const int nstage = stage_doubles(nx, K);
-  const Stager<K> S{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
-  double* rhs_stage = reinterpret_cast<double*>(smem_raw) + nstage;  // IO only
-  T* sm = reinterpret_cast<T*>(smem_raw + sizeof(double) * nstage * (IO ? 2 : 1));
-  T* img = reinterpret_cast<T*>(S.stg);  // chunk image, padded layout, as T
+  const int E = NL * K;
+  const int t0 = c * a.tile, t1 = min(t0 + a.tile, nx);
+  const int eout = E - (t1 - t0);  // first position written
+  int f0 = (t1 - E) % nx;
+  f0 += (f0 < 0) ? nx : 0;
+  const Extent<K> X{nx, NL, lane, E, f0};
+  const int nst = E + E / K;  // doubles of one staged row
+  const bool preload = IO && a.preload && a.rhs_mode == RHS_EVERY;
+  double* ring = reinterpret_cast<double*>(smem_raw);  // preloaded rows 1..m
+  unsigned char* lds = smem_raw + (preload ? sizeof(double) * (size_t)m * nst : 0);
+  double* stg = reinterpret_cast<double*>(lds);
+  T* sm = reinterpret_cast<T*>(lds + sizeof(double) * nst);  // halo slots
+  // streaming case: two chunk images (steps alternate), position p at
+  // slot(p + M), the M positions before 0 a copy of the last M (periodic
+  // wrap, or discarded values of a tile), so that every halo address is
+  // this lane's base plus a constant
+  constexpr int M = ((W - 1 + K - 1) / K) * K;
+  const int nimg = (E + M) + (E + M) / K;
+  T* img0 = reinterpret_cast<T*>(stg);
+  T* img1 = img0 + nimg;
   const int b = lane * (K + 1);
+  const bool ghost = lane * K >= E - M;  // this chunk is also copied before 0
+  // write x as the image of buffer im (and its ghost copy)
+  auto put_image = [&](T* im, const T (&xv)[K]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) im[b + (M + M / K) + k] = xv[k];
+    if (ghost) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) im[b + (M + M / K) + k - NL * (K + 1)] = xv[k];
+    }
+  };
 
-  double v0[K];
-  start_state<K>(a, j, S, v0);
-  if (a.mode == MODE_F) {
-    S.store(a.out + (long long)j * m * nx, 0, v0);
-    if (j == a.nint) return;  // extra block: the last corrected C-point
-  } else if (a.mode == MODE_FC && a.write_row0 && j == 0) {
-    S.store(a.out, 0, v0);
+  // start state (FP64, staged)
+  {
+    double v[K];
+    if (a.zero_in) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) v[q] = 0.0;
+    } else {
+      X.fetch(a.in + (long long)j * a.in_stride * nx, 0, v);
+      if (a.corr) {
+        double cr[K];
+        X.fetch(a.corr + (long long)j * a.corr_stride * nx, 0, cr);
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] += cr[q];
+      }
+    }
+    X.put(stg, v);
   }
+  __syncthreads();
+  const bool store0 = (a.mode == MODE_F && !a.skip_row0) ||
+                      (a.mode == MODE_FC && a.write_row0 && j == 0);
+  if (store0) {
+    double* row = a.out + (a.mode == MODE_F ? (long long)j * m * nx : 0LL);
+    const int b0 = X.first(0);
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int e = eout + lane + q * NL;
+      if (e < E) row[X.at(b0, e)] = stg[Extent<K>::slot(e)];
+    }
+  }
+  if (a.mode == MODE_F && j == a.nint) return;  // extra block: the last C-point
   T x[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) x[k] = (T)v0[k];
+  for (int k = 0; k < K; ++k) x[k] = (T)stg[b + k];
   T tp[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) tp[t] = (T)a.taps[t];
@@ -221,29 +366,43 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
 
   const bool every = IO && a.rhs_mode == RHS_EVERY;
   const bool store_steps = IO && a.mode == MODE_F;
-  double gnext[IO ? K : 1];
-  // right-hand side row of step s into B at its frame shift (coalesced)
-  auto put_rhs = [&](int shift) {
-#pragma unroll
-    for (int q = 0; q < K; ++q)
-      rhs_stage[S.slot(S.local(lane + q * NL, shift))] = gnext[q];
-  };
-  __syncthreads();  // staging area A is free (start_state / stores done)
+  const long long row0 = (long long)j * m;
+  // right-hand side chunks of the next two steps (ga: odd steps, gb: even)
+  double ga[IO ? K : 1], gb[IO ? K : 1];
   if constexpr (IO) {
-    if (every && m >= 1) {
-      S.fetch(a.rhs + ((long long)j * m + 1) * nx, gnext);
-      put_rhs(wrap_hi(a.omin, nx));
-      if (m >= 2) S.fetch(a.rhs + ((long long)j * m + 2) * nx, gnext);
+    if (preload) {
+      // all right-hand side rows into LDS, up to 32/K rows in flight
+      constexpr int B = (32 / K) > 0 ? 32 / K : 1;
+      int shr = 0;
+      for (int s0 = 1; s0 <= m; s0 += B) {
+        double r[B][K];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          shr = wrap_hi(shr + a.omin, nx);
+          if (s0 + i <= m) X.fetch(a.rhs + (row0 + s0 + i) * nx, shr, r[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+          if (s0 + i <= m) X.put(ring + (long long)(s0 + i - 1) * nst, r[i]);
+      }
+    } else if (every) {
+      if (m >= 1) X.chunk(a.rhs + (row0 + 1) * nx, wrap_hi(a.omin, nx), ga);
+      if (m >= 2)
+        X.chunk(a.rhs + (row0 + 2) * nx, wrap_hi(wrap_hi(a.omin, nx) + a.omin, nx), gb);
     }
   }
+  __syncthreads();  // staging area free (start row delivered and stored)
   if constexpr (!kShfl) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) img[b + k] = x[k];
+    put_image(img0, x);
+    __syncthreads();
   }
-  __syncthreads();
 
   int sh = 0;
-  for (int s = 1; s <= m; ++s) {
+  // one step: x <- taps * x (+ g); g is this step's right-hand side chunk
+  auto step = [&](int s, double (&g)[IO ? K : 1], auto ev, auto pl)
+                  __attribute__((always_inline)) {
+    constexpr bool EV = decltype(ev)::value;  // right-hand side every step
+    constexpr bool PL = decltype(pl)::value;  // ... preloaded in LDS
     if constexpr (kShfl) {
       if constexpr (W > 1) {
         T halo[HW];
@@ -283,60 +442,109 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
         for (int k = 0; k < K; ++k) x[k] *= tp[0];
       }
     } else {
-      // stream the window position q (relative to lane*K) from the image
+      // halo positions q = -(W-1)..-1 (relative to lane*K) from the image
+      // of the previous step in batches of NB LDS reads, the next batch in
+      // flight while the current one is consumed; then the own chunk
+      const T* im = (s & 1) ? img0 : img1;
+      constexpr int NB = 12;
+      constexpr int NBAT = (W - 1 + NB - 1) / NB;
       T acc[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) acc[k] = (T)0;
+      T hv[2][NB];
+      auto read_batch = [&](int bi, T (&h)[NB]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int q = -(W - 1); q < K; ++q) {
-        T v;
-        if (q >= 0) {
-          v = x[q >= 0 ? q : 0];
-        } else {
-          int p = lane * K + q;
-          p += (p < 0) ? nx : 0;
-          v = img[S.slot(p)];
+        for (int i = 0; i < NB; ++i) {
+          const int q = -(W - 1) + bi * NB + i;
+          if (q < 0) h[i] = im[b + ((q + M) + (q + M) / K)];
         }
+      };
+      read_batch(0, hv[0]);
 #pragma unroll
-        for (int k = (q > 0 ? q : 0); k < K && k < q + W; ++k) acc[k] = fma(tp[k - q], v, acc[k]);
+      for (int bi = 0; bi < NBAT; ++bi) {
+        if (bi + 1 < NBAT) read_batch(bi + 1, hv[(bi + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int q = -(W - 1) + bi * NB + i;
+          if (q < 0) {
+#pragma unroll
+            for (int k = 0; k < K && k < q + W; ++k) acc[k] = fma(tp[k - q], hv[bi & 1][i], acc[k]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+#pragma unroll
+        for (int k = q; k < K && k < q + W; ++k) acc[k] = fma(tp[k - q], x[q], acc[k]);
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) x[k] = acc[k];
     }
     sh = wrap_hi(sh + a.omin, nx);
     if constexpr (IO) {
-      if (every) {
+      if constexpr (EV && PL) {
+        const double* rr = ring + (long long)(s - 1) * nst + b;
 #pragma unroll
-        for (int k = 0; k < K; ++k) x[k] += (T)rhs_stage[b + k];
+        for (int k = 0; k < K; ++k) x[k] += (T)rr[k];
+      } else if constexpr (EV) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] += (T)g[k];
+        // prefetch the row of step s+2 (clamped to the last row) into the
+        // registers just used: unconditional, so that they stay one
+        // loop-carried value and the load is first waited for two steps on
+        const int sh2 = wrap_hi(wrap_hi(sh + a.omin, nx) + a.omin, nx);
+        X.chunk(a.rhs + (row0 + min(s + 2, m)) * nx, sh2, g);
       }
-      if (every || store_steps || !kShfl) {
-        __syncthreads();  // image and right-hand side of this step consumed
-        if (!kShfl || store_steps) {
+      if (kShfl && store_steps && (s < m || a.write_last)) {
+        // no image: each lane stores its chunk
+        double* row = a.out + (row0 + s) * nx;
+        const int bs = X.first(sh);
 #pragma unroll
-          for (int k = 0; k < K; ++k) img[b + k] = x[k];
-        }
-        if (every && s < m) {
-          put_rhs(wrap_hi(sh + a.omin, nx));
-          if (s + 1 < m) S.fetch(a.rhs + ((long long)j * m + s + 2) * nx, gnext);
-        }
-        __syncthreads();
-        if (store_steps && (s < m || a.write_last)) {
-          double* row = a.out + ((long long)j * m + s) * nx;
-#pragma unroll
-          for (int q = 0; q < K; ++q) {
-            const int i = lane + q * NL;
-            row[i] = (double)img[S.slot(S.local(i, sh))];
-          }
+        for (int k = 0; k < K; ++k) {
+          const int e = lane * K + k;
+          if (e >= eout) row[X.at(bs, e)] = (double)x[k];
         }
       }
-    } else if constexpr (!kShfl) {
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < K; ++k) img[b + k] = x[k];
-      __syncthreads();
     }
-  }
-  finish<T, K>(a, j, S, sh, x, red);
+    if constexpr (!kShfl) {
+      // the other buffer: its last readers (step s-1) passed the barrier
+      // of step s-1 before anyone reaches this write
+      T* im = (s & 1) ? img1 : img0;
+      put_image(im, x);
+      __syncthreads();
+      if (store_steps && (s < m || a.write_last)) {
+        // coalesced stores from the new image (overwritten two steps on)
+        double* row = a.out + (row0 + s) * nx;
+        const int bs = X.first(sh);
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          const int e = lane + q * NL;
+          if (e >= eout) row[X.at(bs, e)] = (double)im[(e + M) + (e + M) / K];
+        }
+      }
+    }
+  };
+  // with a right-hand side in registers, steps in pairs (odd steps use ga,
+  // even ones gb); the loop is written once per source of the right-hand
+  // side so that no register carries a value merged from two paths
+  auto run = [&](auto ev, auto pl) __attribute__((always_inline)) {
+    if constexpr (!decltype(ev)::value) {
+      for (int s = 1; s <= m; ++s) step(s, ga, ev, pl);
+    } else {
+      int s = 1;
+      for (; s + 1 <= m; s += 2) {
+        step(s, ga, ev, pl);
+        step(s + 1, gb, ev, pl);
+      }
+      if (s == m) step(s, ga, ev, pl);
+    }
+  };
+  if (!every) run(std::false_type{}, std::false_type{});
+  else if (preload) run(std::true_type{}, std::true_type{});
+  else run(std::true_type{}, std::false_type{});
+  finish_extent<T, K>(a, j, X, eout, sh, x, stg, red);
 }
 
 // ---------------------------------------------------------------------------
