@@ -33,6 +33,26 @@ __device__ __forceinline__ int wrap_hi(int i, int n) { return i >= n ? i - n : i
 __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Value of lane (l - 1) mod 64 of the wavefront, for lane l (DPP
+// wave_ror:1, no LDS traffic).
+__device__ __forceinline__ int ror1(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float ror1(float v) { return __int_as_float(ror1(__float_as_int(v))); }
+__device__ __forceinline__ double ror1(double v) {
+  return __hiloint2double(ror1(__double2hiint(v)), ror1(__double2loint(v)));
+}
+
+// Row element g of a row (g < 2^29): a 32-bit byte offset from the row's
+// uniform base, which global loads/stores take as a scalar base plus a
+// vector offset (no 64-bit address arithmetic per element).
+__device__ __forceinline__ double ld_row(const double* row, unsigned g) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + (g << 3));
+}
+__device__ __forceinline__ void st_row(double* row, unsigned g, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(row) + (g << 3)) = v;
+}
+
 // Wait for every outstanding vector-memory load of this wavefront
 // (s_waitcnt vmcnt(0), other counters untouched).  Called once after values
 // that stay in registers through a step loop are loaded: without it the
@@ -176,21 +196,21 @@ __device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K
 // chunk order are both free of bank conflicts.
 template <int K>
 struct Extent {
-  int nx, NL, lane, E, f0;  // f0 in [0, n_x), E <= 2 n_x
+  int nx, NL, lane, E, f0;  // f0 in [0, n_x), E <= n_x
   __device__ __forceinline__ static int slot(int e) { return e + e / K; }
   // true point of position 0 at frame shift sh (sh in [0, n_x))
   __device__ __forceinline__ int first(int sh) const { return wrap_hi(f0 + sh, nx); }
-  __device__ __forceinline__ int at(int b, int e) const {
-    int g = b + e;
-    g -= (g >= nx) ? nx : 0;
-    g -= (g >= nx) ? nx : 0;
-    return g;
+  // true point of position e (b = first(sh)); unsigned, so that row
+  // addresses are a uniform base plus a 32-bit lane offset
+  __device__ __forceinline__ unsigned at(int b, int e) const {
+    unsigned g = (unsigned)(b + e);
+    return g >= (unsigned)nx ? g - (unsigned)nx : g;
   }
   // global -> registers, coalesced (element q is position lane + q*NL)
   __device__ __forceinline__ void fetch(const double* row, int sh, double (&r)[K]) const {
     const int b = first(sh);
 #pragma unroll
-    for (int q = 0; q < K; ++q) r[q] = row[at(b, lane + q * NL)];
+    for (int q = 0; q < K; ++q) r[q] = ld_row(row, at(b, lane + q * NL));
   }
   __device__ __forceinline__ void put(double* stg, const double (&r)[K]) const {
 #pragma unroll
@@ -200,7 +220,7 @@ struct Extent {
   __device__ __forceinline__ void chunk(const double* row, int sh, double (&r)[K]) const {
     const int b = first(sh);
 #pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = row[at(b, lane * K + k)];
+    for (int k = 0; k < K; ++k) r[k] = ld_row(row, at(b, lane * K + k));
   }
 };
 
@@ -220,21 +240,22 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
   __syncthreads();
   const int bs = X.first(sh);
   const long long rj = (long long)(j + 1) * nx;
+  const double* grow = a.rhs_mode == RHS_CPOINT ? a.rhs + rj : nullptr;
+  const double* rrow = a.mode == MODE_RES ? a.ref + rj : nullptr;
+  double* orow = a.out + (a.mode == MODE_FC ? (long long)(j + a.out_off) * nx : rj);
   double ss = 0.0;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     const int e = eout + lane + q * NL;
     if (e < E) {
-      const int g = X.at(bs, e);
+      const unsigned g = X.at(bs, e);
       double v = stg[Extent<K>::slot(e)];
-      if (a.rhs_mode == RHS_CPOINT) v += a.rhs[rj + g];
-      if (a.mode == MODE_FC) {
-        a.out[(long long)(j + a.out_off) * nx + g] = v;
-      } else {
-        v -= a.ref[rj + g];
-        a.out[rj + g] = v;
+      if (grow) v += ld_row(grow, g);
+      if (rrow) {
+        v -= ld_row(rrow, g);
         ss += v * v;
       }
+      st_row(orow, g, v);
     }
   }
   if (a.mode == MODE_RES) {
@@ -243,7 +264,7 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         const int e = eout + lane + q * NL;
-        if (e < E) a.out[X.at(b0, e)] = 0.0;
+        if (e < E) st_row(a.out, X.at(b0, e), 0.0);
       }
     }
     if (a.partial) {
@@ -272,7 +293,7 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
 //
 // Two ways to apply the stencil, chosen at compile time:
 //  * W-1 <= K (halo within the left neighbour lane): in place, right to
-//    left, halo values by cross-lane permute inside the wavefront and from a
+//    left, halo values by a DPP lane rotate inside the wavefront and from a
 //    2*H-value LDS slot per wavefront across wavefronts;
 //  * W-1 > K (wide coarse operators): the chunk image of every lane sits in
 //    LDS (padded layout), each output accumulates while halo values stream
@@ -352,7 +373,7 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       const int e = eout + lane + q * NL;
-      if (e < E) row[X.at(b0, e)] = stg[Extent<K>::slot(e)];
+      if (e < E) st_row(row, X.at(b0, e), stg[Extent<K>::slot(e)]);
     }
   }
   if (a.mode == MODE_F && j == a.nint) return;  // extra block: the last C-point
@@ -414,16 +435,20 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
           }
           __syncthreads();
         }
-        const int srcl = (lw + 63) & 63;
         const int pw = (wave + nwave - 1) % nwave;
+        // halo[h]: the point W-1-h to the left of lane*K, element
+        // K-(W-1-h) of the left neighbour lane: a DPP rotate inside the
+        // wavefront, and for lane 0 the previous wavefront's edge slot
+        // (read by all lanes at one address, then selected)
+        T edge[HW];
+        if (nwave > 1) {
+#pragma unroll
+          for (int h = 0; h < W - 1; ++h) edge[h] = slot[pw * H + (h + H - (W - 1))];
+        }
 #pragma unroll
         for (int h = 0; h < W - 1; ++h) {
-          // halo[h]: the point W-1-h to the left of lane*K, element
-          // K-(W-1-h) of the left neighbour lane
-          const int e = K - (W - 1 - h);
-          T v = __shfl(x[e], srcl, 64);
-          if (nwave > 1 && lw == 0) v = slot[pw * H + (e - (K - H))];
-          halo[h] = v;
+          const T v = ror1(x[K - (W - 1 - h)]);
+          halo[h] = (nwave > 1 && lw == 0) ? edge[h] : v;
         }
         // in place, right to left: x[k] <- sum_t tp[t] * x[k - t]
 #pragma unroll
@@ -485,7 +510,7 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
     sh = wrap_hi(sh + a.omin, nx);
     if constexpr (IO) {
       if constexpr (EV && PL) {
-        const double* rr = ring + (long long)(s - 1) * nst + b;
+        const double* rr = ring + (long long)(s - 1) * nst + b;  // (preloaded)
 #pragma unroll
         for (int k = 0; k < K; ++k) x[k] += (T)rr[k];
       } else if constexpr (EV) {
@@ -504,7 +529,7 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const int e = lane * K + k;
-          if (e >= eout) row[X.at(bs, e)] = (double)x[k];
+          if (e >= eout) st_row(row, X.at(bs, e), (double)x[k]);
         }
       }
     }
@@ -521,7 +546,7 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
 #pragma unroll
         for (int q = 0; q < K; ++q) {
           const int e = lane + q * NL;
-          if (e >= eout) row[X.at(bs, e)] = (double)im[(e + M) + (e + M) / K];
+          if (e >= eout) st_row(row, X.at(bs, e), (double)im[(e + M) + (e + M) / K]);
         }
       }
     }
