@@ -68,7 +68,10 @@ extern "C" {
 #define MGRIT_RELAX_FCF 0    /* FCF-relaxation (Sec. 2.2, the paper's choice) */
 #define MGRIT_RELAX_F 1      /* F-relaxation (Parareal)                       */
 #define MGRIT_FP64 0         /* all arithmetic in FP64                        */
-#define MGRIT_FP32_RELAX 1   /* FP32 relaxation inside FP64 iterative refinement */
+#define MGRIT_FP32_RELAX 1   /* FP32 relaxation of FP64 iterates: with FCF,
+                                the second fine pass acts on the C-point
+                                update in FP32; with F-relaxation, FP32 inner
+                                cycles inside FP64 iterative refinement     */
 
 /* coarse-operator pattern rules for mgrit_psi_optimize */
 #define MGRIT_PSI_AUTO 0     /* ETA for SDIRK, WINDOW for ERK                 */
@@ -93,7 +96,8 @@ typedef struct mgrit_plan_s* mgrit_plan_t;
 /* Statistics of the last mgrit_solve on a plan. */
 typedef struct {
     int iterations;        /* fine-level coarse-grid corrections applied      */
-    int outer_iterations;  /* FP64 refinement steps (MGRIT_FP32_RELAX), else 0 */
+    int outer_iterations;  /* MGRIT_FP32_RELAX: FP64 fine passes (FCF) or
+                              FP64 refinement steps (F-relaxation), else 0 */
     int fine_passes_fp64;  /* fine-level relaxation passes run in FP64        */
     int fine_passes_fp32;  /* fine-level relaxation passes run in FP32        */
     double final_residual; /* sqrt(dx dt sum r^2) of the returned iterate     */
@@ -176,8 +180,8 @@ int mgrit_plan_create(mgrit_plan_t* plan, int nx, int nt, double alpha,
  *   maxit:     maximum coarse-grid corrections (>= 0).
  *   u_out_dev: output per out_kind (MGRIT_OUT_*), may be NULL for NONE.
  *   res_hist_host: may be NULL, else room for maxit+1 doubles: the
- *              residual norm before each correction (FP64 refinement
- *              residuals for MGRIT_FP32_RELAX).
+ *              residual norm before each correction (for MGRIT_FP32_RELAX
+ *              with F-relaxation: the FP64 refinement residuals).
  *   iters_out: may be NULL; receives the number of corrections.
  * Returns MGRIT_ENOTCONV if maxit is reached (outputs still written),
  * MGRIT_EDIVERGED on a non-finite norm.  Synchronous. */

@@ -35,7 +35,11 @@ struct RelaxArgs {
   const double* rhs;
   const double* ref;       // MODE_RES: the C-points v being tested
   double* out;
-  double* partial;         // MODE_RES: sum of r^2 per interval (may be null)
+  double* partial;         // sum of the squared outputs per workgroup (MODE_RES:
+                           // of r, MODE_FC: of out[j+out_off]); may be null
+  double* delta;           // MODE_FC, may be null: also delta[j+1] =
+                           // out[j+out_off] - (in[j+1] + corr[j+1]), the
+                           // update of C-point j+1 (row 0 set to 0)
   const double* taps;      // stencil: weights of the window offsets omin..omin+W-1
   const int* tap_off;      // generic kernel: offsets in [0, nx)
   const void* sdirk;       // SDIRK kernel: device SdirkDev

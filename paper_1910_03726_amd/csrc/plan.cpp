@@ -475,7 +475,7 @@ void Plan::end_util(int cls, hipEvent_t e0) {
 // Relaxation on level l (0 = fine).  mode: MODE_FC / MODE_RES / MODE_F.
 int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride,
                 const double* corr, const double* rhs, int rhs_mode, double* out,
-                double* partial, int steps) {
+                double* partial, int steps, double* delta) {
   Level& L = lev[l];
   const OpDesc& op = L.op;
   RelaxArgs a = base_args(*this, op);
@@ -489,12 +489,13 @@ int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride
   a.m = steps;
   a.nint = L.nc;
   a.out = out;
+  a.partial = partial;
   if (mode == MODE_FC) {
     a.out_off = 1;
     a.write_row0 = 1;
+    a.delta = delta;
   } else if (mode == MODE_RES) {
     a.ref = in;
-    a.partial = partial;
   }
   const int grid = L.nc + (mode == MODE_F ? 1 : 0);
   if (l == 0) fine_dof_steps += (double)L.nc * steps * nx;
@@ -998,10 +999,56 @@ static int solve_fp64(Plan* P, const double* u0, const double* uinit, double tol
   return status;
 }
 
-// FP32 relaxation inside FP64 iterative refinement: the FP64 residual r of
-// the iterate u, inner MGRIT cycles with FP32 relaxation on the error
-// system e^{j+1} = Phi^m e^j + r^{j+1} (sequential coarse solve, residual
-// subtraction and norms in FP64), then u += e in FP64.
+// FP32 relaxation as the correction of FP64 FCF-relaxed iterates.  With u
+// the current C-points (cur + corr), the FCF-relaxed iterate of the FP64
+// solver is v = FC(u) and its residual r_{j+1} = Phi^m v_j - v_{j+1}.
+// Writing v = u + d (d the C-relaxation update, d^0 = 0) gives exactly
+// r_{j+1} = Phi^m d_j, because Phi^m u_j = v_{j+1}: the second fine pass
+// acts only on the small update d and runs in FP32 with errors relative to
+// |d|, while the C-point iterate, its FC pass, the coarse correction and
+// the norms stay FP64.  Iteration by iteration this is the FP64 solver.
+static int solve_mixed(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
+                       double* u_out, int out_kind, double* hist, int* iters) {
+  int rc = init_iterate(P, u0, uinit, P->Va);
+  if (rc) return rc;
+  double* cur = P->Va;
+  double* nxt = P->Vb;
+  double* d = P->U;
+  const double* corr = nullptr;
+  int status = MGRIT_ENOTCONV;
+  int it = 0;
+  for (;; ++it) {
+    if ((rc = P->relax(0, 0, MODE_FC, cur, 1, corr, nullptr, RHS_NONE, nxt, nullptr, P->m, d)))
+      return rc;
+    P->stats.fine_passes_fp64 += 1;
+    if ((rc = P->relax(0, 1, MODE_FC, d, 1, nullptr, nullptr, RHS_NONE, P->lev[0].R,
+                       P->partial, P->m)))
+      return rc;
+    P->stats.fine_passes_fp32 += 1;
+    double res = 0.0;
+    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
+    if (hist) hist[it] = res;
+    P->stats.final_residual = res;
+    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
+    if (res <= tol) { status = MGRIT_OK; break; }
+    if (it >= maxit) { status = MGRIT_ENOTCONV; break; }
+    if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 0))) return rc;
+    corr = P->lev[1].X;
+    std::swap(cur, nxt);
+  }
+  P->stats.iterations = it;
+  P->stats.outer_iterations = it + 1;
+  if (iters) *iters = it;
+  if ((rc = finish_output(P, nxt, u_out, out_kind))) return rc;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
+  return status;
+}
+
+// F-relaxation (Parareal) with FP32 relaxation, as FP64 iterative
+// refinement: the FP64 residual r of the iterate u, inner MGRIT cycles with
+// FP32 relaxation on the error system e^{j+1} = Phi^m e^j + r^{j+1}
+// (sequential coarse solve, residual subtraction and norms in FP64), then
+// u += e in FP64.
 static int solve_ir(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
                     double* u_out, int out_kind, double* hist, int* iters) {
   const int nc = P->nt / P->m;
@@ -1079,9 +1126,11 @@ int mgrit_solve(mgrit_plan_t plan, const double* u0, const double* uinit, double
   Plan* P = reinterpret_cast<Plan*>(plan);
   std::memset(&P->stats, 0, sizeof P->stats);
   auto t0 = std::chrono::steady_clock::now();
-  int rc = P->precision == MGRIT_FP32_RELAX
-               ? solve_ir(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
-               : solve_fp64(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters);
+  int rc = P->precision != MGRIT_FP32_RELAX
+               ? solve_fp64(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
+               : P->relax_kind == MGRIT_RELAX_FCF
+                     ? solve_mixed(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
+                     : solve_ir(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters);
   auto t1 = std::chrono::steady_clock::now();
   P->stats.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   return rc;

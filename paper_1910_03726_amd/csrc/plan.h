@@ -99,7 +99,7 @@ struct Plan {
   void end_util(int cls, hipEvent_t e0);
   int relax(int l, int prec, int mode, const double* in, long long in_stride,
             const double* corr, const double* rhs, int rhs_mode, double* out,
-            double* partial, int steps);
+            double* partial, int steps, double* delta = nullptr);
   int copy_cpoints(int l, int prec, const double* in, long long in_stride,
                    const double* corr, double* out);
   int sequential(const double* g);

@@ -167,21 +167,47 @@ __device__ __forceinline__ void finish(const RelaxArgs& a, int j, const Stager<K
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += g[k];
   }
-  if (a.mode == MODE_FC) {
-    S.store(a.out + (long long)(j + a.out_off) * nx, sh, v);
-    return;
-  }
-  double rf[K];
-  S.load(a.ref + (long long)(j + 1) * nx, sh, rf);
   double ss = 0.0;
+  if (a.mode == MODE_FC) {
+    if (a.partial) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    v[k] -= rf[k];
-    ss += v[k] * v[k];
-  }
-  S.store(a.out + (long long)(j + 1) * nx, sh, v);
-  if (j == 0) {
-    for (int i = S.lane; i < nx; i += S.NL) a.out[i] = 0.0;  // r^0 = 0
+      for (int k = 0; k < K; ++k) ss += v[k] * v[k];
+    }
+    S.store(a.out + (long long)(j + a.out_off) * nx, sh, v);
+    if (a.delta) {
+      // update of C-point j+1: out - (in + corr), row 0 = 0
+      double u[K];
+      if (a.zero_in) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k] = 0.0;
+      } else {
+        S.load(a.in + (long long)(j + 1) * a.in_stride * nx, sh, u);
+      }
+      if (a.corr) {
+        double c[K];
+        S.load(a.corr + (long long)(j + 1) * a.corr_stride * nx, sh, c);
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k] += c[k];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) u[k] = v[k] - u[k];
+      S.store(a.delta + (long long)(j + 1) * nx, sh, u);
+      if (j == 0) {
+        for (int i = S.lane; i < nx; i += S.NL) a.delta[i] = 0.0;
+      }
+    }
+  } else {
+    double rf[K];
+    S.load(a.ref + (long long)(j + 1) * nx, sh, rf);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] -= rf[k];
+      ss += v[k] * v[k];
+    }
+    S.store(a.out + (long long)(j + 1) * nx, sh, v);
+    if (j == 0) {
+      for (int i = S.lane; i < nx; i += S.NL) a.out[i] = 0.0;  // r^0 = 0
+    }
   }
   if (a.partial) {
     const double s = block_sum(ss, red);
@@ -243,6 +269,11 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
   const double* grow = a.rhs_mode == RHS_CPOINT ? a.rhs + rj : nullptr;
   const double* rrow = a.mode == MODE_RES ? a.ref + rj : nullptr;
   double* orow = a.out + (a.mode == MODE_FC ? (long long)(j + a.out_off) * nx : rj);
+  // FC with delta: the current C-point j+1 (in + corr) and the update row
+  const bool dl = a.mode == MODE_FC && a.delta;
+  const double* urow = (dl && !a.zero_in) ? a.in + (long long)(j + 1) * a.in_stride * nx : nullptr;
+  const double* crow = (dl && a.corr) ? a.corr + (long long)(j + 1) * a.corr_stride * nx : nullptr;
+  double* drow = dl ? a.delta + rj : nullptr;
   double ss = 0.0;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
@@ -251,26 +282,29 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
       const unsigned g = X.at(bs, e);
       double v = stg[Extent<K>::slot(e)];
       if (grow) v += ld_row(grow, g);
-      if (rrow) {
-        v -= ld_row(rrow, g);
-        ss += v * v;
-      }
+      if (rrow) v -= ld_row(rrow, g);
+      ss += v * v;
       st_row(orow, g, v);
+      if (dl) {
+        double u = urow ? ld_row(urow, g) : 0.0;
+        if (crow) u += ld_row(crow, g);
+        st_row(drow, g, v - u);
+      }
     }
   }
-  if (a.mode == MODE_RES) {
-    if (j == 0) {  // r^0 = 0 over this tile
-      const int b0 = X.first(0);
+  // row 0: r^0 = 0 (MODE_RES), delta^0 = 0 (MODE_FC with delta)
+  double* zrow = a.mode == MODE_RES ? a.out : (dl ? a.delta : nullptr);
+  if (zrow && j == 0) {
+    const int b0 = X.first(0);
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        const int e = eout + lane + q * NL;
-        if (e < E) st_row(a.out, X.at(b0, e), 0.0);
-      }
+    for (int q = 0; q < K; ++q) {
+      const int e = eout + lane + q * NL;
+      if (e < E) st_row(zrow, X.at(b0, e), 0.0);
     }
-    if (a.partial) {
-      const double s = block_sum(ss, red);
-      if (lane == 0) a.partial[blockIdx.x] = s;
-    }
+  }
+  if (a.partial) {
+    const double s = block_sum(ss, red);
+    if (lane == 0) a.partial[blockIdx.x] = s;
   }
 }
 
@@ -616,10 +650,22 @@ __global__ void __launch_bounds__(256) k_generic(RelaxArgs a) {
   }
   if (a.mode == MODE_FC) {
     const double* gc = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;
+    double ss = 0.0;
     for (int p = tid; p < nx; p += NT) {
       double v = (double)cur[p];
       if (gc) v += gc[p];
       a.out[(long long)(j + a.out_off) * nx + p] = v;
+      ss += v * v;
+      if (a.delta) {
+        double u = a.zero_in ? 0.0 : a.in[(long long)(j + 1) * a.in_stride * nx + p];
+        if (a.corr) u += a.corr[(long long)(j + 1) * a.corr_stride * nx + p];
+        a.delta[(long long)(j + 1) * nx + p] = v - u;
+        if (j == 0) a.delta[p] = 0.0;
+      }
+    }
+    if (a.partial) {
+      const double s = block_sum(ss, red);
+      if (tid == 0) a.partial[j] = s;
     }
   } else if (a.mode == MODE_RES) {
     const double* gc = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;

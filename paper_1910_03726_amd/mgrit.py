@@ -226,6 +226,7 @@ class Plan:
         self.nx, self.nt, self.m, self.levels = int(nx), int(nt), int(m), int(levels)
         self.scheme = scheme
         self.precision = precision
+        self.relax = relax
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self._stream = stream
@@ -282,7 +283,10 @@ class Plan:
         if rc not in (OK, ENOTCONV, EDIVERGED):
             raise MgritError(rc, "mgrit_solve")
         st = self.stats()
-        nh = (st.outer_iterations if self.precision == "fp32" else it.value) + 1
+        # one norm per correction; FP32 Parareal (F-relaxation) records one
+        # per FP64 refinement step instead
+        refine = self.precision == "fp32" and self.relax == "F"
+        nh = (st.outer_iterations if refine else it.value) + 1
         return SolveResult(rc, it.value, list(hist[:nh]), u_out, st)
 
     def phi_apply_batch(self, inp, out, ksteps):

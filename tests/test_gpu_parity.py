@@ -218,6 +218,51 @@ def test_fp32_relaxation_refinement():
     assert _rel(_n(g.out), seq) < 1e-8
 
 
+@pytest.mark.parametrize("s,nx,nt,m,L,cycle", [
+    ("ERK3", 256, 2048, 8, 3, "V"), ("ERK5", 512, 4096, 8, 3, "F"),
+    ("ERK1", 128, 1024, 4, 2, "V"), ("SDIRK3", 256, 1024, 4, 2, "V")])
+def test_fp32_relaxation_tracks_the_fp64_iteration(s, nx, nt, m, L, cycle):
+    # With FCF the FP32 form is the FP64 iteration with its second fine
+    # pass applied to the C-point update d (r = Phi^m d in exact
+    # arithmetic): same iteration count, residual history equal up to FP32
+    # rounding of |d|, converged to the FP64 solution.
+    c = rk.paper_cfl(s) if s.startswith("ERK") else 4.0
+    d = rk.Discretization(s, nx, c)
+    psi = _oracle_hierarchy(d, m, L)  # window rule (ERK) / eta rule (SDIRK)
+    u0 = inputs.fourier_u0(nx, 8, 0)
+    uinit = inputs.random_iterate(nt // m + 1, nx, 1)
+    runs = {}
+    for prec in ("fp64", "fp32"):
+        with M.Plan(nx, nt, c, s, m, L, psi, cycle=cycle, precision=prec) as P:
+            runs[prec] = (P.solve(_t(u0), _t(uinit), tol=1e-12, maxit=40, out="cpoints"), P.stats())
+    (g64, _), (g32, st) = runs["fp64"], runs["fp32"]
+    assert g64.converged and g32.converged
+    assert abs(g32.iters - g64.iters) <= 1
+    assert st.fine_passes_fp32 == g32.iters + 1 and st.fine_passes_fp64 == g32.iters + 1
+    h64, h32 = np.array(g64.hist), np.array(g32.hist)
+    n = min(len(h64), len(h32))
+    big = h64[:n] > 1e-6 * h64[0]
+    assert np.all(np.abs(h32[:n][big] - h64[:n][big]) <= 1e-4 * h64[:n][big])
+    seq = d.time_stepping(u0, nt, every=m)
+    assert _rel(_n(g32.out), seq) < 1e-9
+
+
+def test_fp32_parareal_refinement():
+    # F-relaxation with FP32 relaxation: FP32 inner cycles inside FP64
+    # iterative refinement reach the FP64 solution.
+    s, nx, nt, m, L = "ERK3", 256, 1024, 4, 2
+    c = rk.paper_cfl(s)
+    d = rk.Discretization(s, nx, c)
+    psi = _oracle_hierarchy(d, m, L)
+    u0 = inputs.fourier_u0(nx, 8, 0)
+    with M.Plan(nx, nt, c, s, m, L, psi, relax="F", precision="fp32") as P:
+        g = P.solve(_t(u0), None, tol=1e-10, maxit=60, out="cpoints")
+        st = P.stats()
+    assert g.converged and g.hist[-1] <= 1e-10
+    assert st.fine_passes_fp32 > 0 and st.outer_iterations >= 1
+    assert _rel(_n(g.out), d.time_stepping(u0, nt, every=m)) < 1e-8
+
+
 def test_errors():
     with pytest.raises(M.MgritError) as e:
         M.Plan(64, 256, 1.2, "ERK1", 4, 2, IDENT)
