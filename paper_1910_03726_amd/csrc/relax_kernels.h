@@ -33,14 +33,17 @@ __device__ __forceinline__ int wrap_hi(int i, int n) { return i >= n ? i - n : i
 __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-// Value of lane (l - 1) mod 64 of the wavefront, for lane l (DPP
-// wave_ror:1, no LDS traffic).
-__device__ __forceinline__ int ror1(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xf, 0xf, false);
+// For lane l > 0 the value v of lane l - 1 of the wavefront, for lane 0
+// `old` (DPP wave_shr:1 without bound control: no LDS traffic).
+__device__ __forceinline__ int shr1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
 }
-__device__ __forceinline__ float ror1(float v) { return __int_as_float(ror1(__float_as_int(v))); }
-__device__ __forceinline__ double ror1(double v) {
-  return __hiloint2double(ror1(__double2hiint(v)), ror1(__double2loint(v)));
+__device__ __forceinline__ float shr1(float old, float v) {
+  return __int_as_float(shr1(__float_as_int(old), __float_as_int(v)));
+}
+__device__ __forceinline__ double shr1(double old, double v) {
+  return __hiloint2double(shr1(__double2hiint(old), __double2hiint(v)),
+                          shr1(__double2loint(old), __double2loint(v)));
 }
 
 // Row element g of a row (g < 2^29): a 32-bit byte offset from the row's
@@ -327,8 +330,8 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
 //
 // Two ways to apply the stencil, chosen at compile time:
 //  * W-1 <= K (halo within the left neighbour lane): in place, right to
-//    left, halo values by a DPP lane rotate inside the wavefront and from a
-//    2*H-value LDS slot per wavefront across wavefronts;
+//    left, halo values by a DPP lane shift inside the wavefront and, for
+//    lane 0, from a 2*H-value LDS slot per wavefront;
 //  * W-1 > K (wide coarse operators): the chunk image of every lane sits in
 //    LDS (padded layout), each output accumulates while halo values stream
 //    from LDS one at a time (registers ~2K instead of K+W).
@@ -462,28 +465,19 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
       if constexpr (W > 1) {
         T halo[HW];
         T* slot = sm + (s & 1) * nwave * H;
-        if (nwave > 1) {
-          if (lw == 63) {
+        if (lw == 63) {
 #pragma unroll
-            for (int e = 0; e < H; ++e) slot[wave * H + e] = x[K - H + e];
-          }
-          __syncthreads();
+          for (int e = 0; e < H; ++e) slot[wave * H + e] = x[K - H + e];
         }
+        __syncthreads();
         const int pw = (wave + nwave - 1) % nwave;
         // halo[h]: the point W-1-h to the left of lane*K, element
-        // K-(W-1-h) of the left neighbour lane: a DPP rotate inside the
-        // wavefront, and for lane 0 the previous wavefront's edge slot
-        // (read by all lanes at one address, then selected)
-        T edge[HW];
-        if (nwave > 1) {
+        // K-(W-1-h) of the left neighbour lane: a DPP shift inside the
+        // wavefront over the previous wavefront's edge value (read by all
+        // lanes at one address), which lane 0 keeps
 #pragma unroll
-          for (int h = 0; h < W - 1; ++h) edge[h] = slot[pw * H + (h + H - (W - 1))];
-        }
-#pragma unroll
-        for (int h = 0; h < W - 1; ++h) {
-          const T v = ror1(x[K - (W - 1 - h)]);
-          halo[h] = (nwave > 1 && lw == 0) ? edge[h] : v;
-        }
+        for (int h = 0; h < W - 1; ++h)
+          halo[h] = shr1(slot[pw * H + (h + H - (W - 1))], x[K - (W - 1 - h)]);
         // in place, right to left: x[k] <- sum_t tp[t] * x[k - t]
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
