@@ -142,6 +142,29 @@ def test_mgrit_counts_and_history(scheme, nx, nt, m, levels, cycle, widths):
     assert _rel(_n(g.out), R.cpoints) < 1e-9
 
 
+@pytest.mark.parametrize("scheme,nx,nt,m,levels", [
+    ("ERK3", 8192, 512, 8, 2), ("ERK5", 8192, 256, 8, 2), ("ERK3", 8192, 256, 4, 3)])
+def test_tiled_fine_level(scheme, nx, nt, m, levels):
+    # Few long intervals: the fine level runs spatially tiled (extents with
+    # upwind ghost zones, ragged last tile); counts, history and solution
+    # as the oracle MGRIT, and phi_apply_batch through the same tiles.
+    d, R, g, u0 = _compare(scheme, nx, nt, m, levels)
+    assert R.status == "converged" and g.converged
+    _check_hist(g, R)
+    assert _rel(_n(g.out), R.cpoints) < 1e-9
+    c = rk.paper_cfl(scheme)
+    psi = _oracle_hierarchy(d, m, levels)
+    with M.Plan(nx, nt, c, scheme, m, levels, psi) as P:
+        desc = P.describe()
+        U = np.random.default_rng(3).standard_normal((3, nx))
+        out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
+        for k in (1, m):
+            P.phi_apply_batch(_t(U), out, k)
+            torch.cuda.synchronize()
+            assert _rel(_n(out), d.propagate(U, k)) < 2e-14 * k
+    assert "plain:" in desc.split(";")[0], desc
+
+
 @pytest.mark.parametrize("scheme,nx,nt,m,levels,cycle", [
     ("ERK3", 256, 1024, 8, 2, "V"), ("ERK5", 128, 1024, 4, 4, "F"),
     ("SDIRK3", 256, 512, 16, 2, "V"), ("ERK1", 64, 256, 4, 3, "V")])
