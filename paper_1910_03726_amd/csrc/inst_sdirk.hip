@@ -1,6 +1,6 @@
 // k_sdirk and k_generic instantiations for one precision (MGR_PREC 0/1).
 #include "registry.h"
-#include "relax_kernels.h"
+#include "sdirk_kernels.h"
 
 #ifndef MGR_PREC
 #error "MGR_PREC must be defined"
