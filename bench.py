@@ -200,7 +200,7 @@ def _serve_run(reqs, u0s, arrivals, slots, setup_threads, budget):
     return res, makespan, st
 
 
-def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
+def serving(n, torch, slots=8, setup_threads=16, budget_gib=128):
     """The serving mix: saturated throughput, then Poisson arrivals at 80% of
     it (p50/p99 latency); the plain FP64 per-solve form on a 10% sample."""
     import numpy as np
@@ -216,19 +216,17 @@ def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
     res2, span2, st2 = _serve_run(reqs, u0s, arr, slots, setup_threads, budget)
     lat = np.array([r.latency_ms for r in res2])
     lat_sat = np.array([r.latency_ms for r in res])
-    # plain per-solve FP64: fresh setup and plan per request, one at a time
-    sample = reqs[::10]
+    # plain per-solve FP64: the same setup and plan path, one request at a
+    # time (submit, wait, next) with one setup thread and one slot
+    sample = [dict(q, precision="fp64") for q in reqs[::10]]
     t0 = time.perf_counter()
     sdof = 0
-    for q in sample:
-        psi, _ = M.psi_optimize(q["scheme"], q["cfl"], q["nx"], q["m"],
-                                _auto_levels(q["nt"], q["m"]))
-        with M.Plan(q["nx"], q["nt"], q["cfl"], q["scheme"], q["m"],
-                    _auto_levels(q["nt"], q["m"]), psi) as P:
-            P.set_seed(q["init_seed"])
-            u0 = torch.tensor(inputs.request_u0(q), dtype=torch.float64, device="cuda")
-            P.solve(u0, None, tol=TOL, maxit=100, out="final")
-        sdof += q["nx"] * q["nt"]
+    with M.Server(budget, slots=1, setup_threads=1) as S1:
+        for q in sample:
+            r, _ = S1.wait(S1.submit(q["nx"], q["nt"], q["scheme"], q["cfl"], q["m"],
+                                     inputs.request_u0(q), precision="fp64",
+                                     seed=q["init_seed"]), q["nx"])
+            sdof += q["nx"] * q["nt"]
     tb = time.perf_counter() - t0
     return {"requests": n, "completed_ok": ok, "slots": slots,
             "setup_threads": setup_threads, "hbm_budget_gib": budget_gib,
@@ -244,7 +242,7 @@ def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
                               "p50_ms": round(float(np.percentile(lat, 50)), 3),
                               "p99_ms": round(float(np.percentile(lat, 99)), 3)},
             "per_solve_fp64": {"sample": f"{len(sample)} of {n} requests (every 10th), "
-                                         "one at a time, fresh setup and plan each",
+                                         "FP64, one at a time: setup, plan, solve, release",
                                "dof_per_s": sdof / tb,
                                "ms_per_request": round(1e3 * tb / len(sample), 3)},
             "serving_speedup_vs_per_solve": round((dof / span) / (sdof / tb), 2)}

@@ -149,10 +149,14 @@ int mgrit_phi_taps(int scheme, double cfl, int nx, int capacity, int* offsets,
  *   MGRIT_PSI_REDISC: ERK only; Psi_l = the ERK stencil at Courant number
  *       m^(l-1) c (no least squares).
  * Weights w_k = 1/(1 - |lambda_k| + 1e-6)^2 on the eigenvalues of Phi_l.
+ * Eq. (9) is solved in its real form: for a real stepper the rows k and
+ * n_x - k are complex conjugates, so the minimiser over complex weights is
+ * real and equals the least-squares solution over k <= n_x/2 with real and
+ * imaginary parts as separate equations (Householder QR).
  * out[l-2] for l = 2..levels must carry arrays with room for out[.].nnz
  * taps (capacity on input, count on output).  *max_imag (may be NULL)
- * receives the largest imaginary part over all levels; above 1e-8 the call
- * returns MGRIT_EIMAG (outputs still written).  Host only. */
+ * receives the largest imaginary part of the weights, 0 in the real form
+ * (MGRIT_EIMAG above 1e-8).  Host only. */
 int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels,
                        int rule, const int* widths, double eta,
                        mgrit_taps* out, double* max_imag);

@@ -266,59 +266,82 @@ static cd ipow(cd z, int m) {
 // ---------------------------------------------------------------------------
 double lsq_psi(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
                std::vector<double>& wout) {
+  // Rows k of eq. (9): sqrt(w_k) [e^{-2 pi i k o_t / n}]_t against
+  // sqrt(w_k) lambda_k^m.  The symbols of a real stencil satisfy
+  // lambda_{n-k} = conj(lambda_k), so rows k and n-k are conjugate and, for
+  // real weights psi, contribute equal residuals: the least-squares problem
+  // is the real one over k = 0..n/2 with the real and imaginary parts of
+  // each row as two equations (scaled by sqrt 2 where k and n-k differ).
+  // Its minimiser is the (real) minimiser of the complex problem; solved by
+  // Householder QR on column-major real arrays.
   const int n = (int)lam.size();
   const int v = (int)offs.size();
   std::vector<cd> w;
   roots_of_unity(n, w);
-  std::vector<cd> M((size_t)n * v), b(n);
-  for (int k = 0; k < n; ++k) {
-    double a = std::abs(lam[k]);
-    double sw = 1.0 / (1.0 - a + 1e-6);  // sqrt of w(|lambda|) = 1/(1-|l|+eps)^2
-    b[k] = sw * ipow(lam[k], m);
+  const int kh = n / 2;
+  std::vector<int> rows_k;  // (k, part): part 0 real, 1 imaginary
+  std::vector<int> rows_p;
+  for (int k = 0; k <= kh; ++k) {
+    rows_k.push_back(k);
+    rows_p.push_back(0);
+    const bool self = (k == 0) || (2 * k == n);
+    if (!self) {
+      rows_k.push_back(k);
+      rows_p.push_back(1);
+    }
+  }
+  const int nr = (int)rows_k.size();
+  std::vector<double> A((size_t)nr * v), bb(nr);
+  for (int r = 0; r < nr; ++r) {
+    const int k = rows_k[r];
+    const bool self = (k == 0) || (2 * k == n);
+    const double sc = self ? 1.0 : std::sqrt(2.0);
+    const double sw = sc / (1.0 - std::abs(lam[k]) + 1e-6);  // sqrt w = 1/(1-|l|+eps)
+    const cd rhs = ipow(lam[k], m);
+    bb[r] = sw * (rows_p[r] ? rhs.imag() : rhs.real());
     for (int t = 0; t < v; ++t) {
-      long long o = ((offs[t] % n) + n) % n;
-      M[(size_t)t * n + k] = sw * w[(int)((k * o) % n)];
+      const long long o = ((offs[t] % n) + n) % n;
+      const cd e = w[(int)((k * o) % n)];
+      A[(size_t)t * nr + r] = sw * (rows_p[r] ? e.imag() : e.real());
     }
   }
-  for (int j = 0; j < v; ++j) {
-    cd* col = &M[(size_t)j * n];
-    double nrm2 = 0.0;
-    for (int i = j; i < n; ++i) nrm2 += std::norm(col[i]);
-    double nrm = std::sqrt(nrm2);
+  auto dot = [nr](const double* x, const double* y, int j) {
+    double s0 = 0.0, s1 = 0.0;
+    int i = j;
+    for (; i + 1 < nr; i += 2) {
+      s0 += x[i] * y[i];
+      s1 += x[i + 1] * y[i + 1];
+    }
+    if (i < nr) s0 += x[i] * y[i];
+    return s0 + s1;
+  };
+  std::vector<double> diag(v, 0.0);
+  for (int j = 0; j < v && j < nr; ++j) {
+    double* h = &A[(size_t)j * nr];
+    const double nrm2 = dot(h, h, j);
+    const double nrm = std::sqrt(nrm2);
     if (nrm == 0.0) continue;
-    cd x0 = col[j];
-    cd phase = std::abs(x0) > 0 ? x0 / std::abs(x0) : cd(1.0);
-    cd alpha = -phase * nrm;
-    std::vector<cd> h(col + j, col + n);
-    h[0] -= alpha;
-    double hn2 = 0.0;
-    for (auto& x : h) hn2 += std::norm(x);
+    const double x0 = h[j];
+    const double alpha = x0 >= 0.0 ? -nrm : nrm;
+    h[j] = x0 - alpha;  // reflector stored in place of the column
+    const double hn2 = nrm2 - x0 * x0 + h[j] * h[j];
+    diag[j] = alpha;
     if (hn2 == 0.0) continue;
-    for (int k = j; k < v; ++k) {
-      cd* ck = &M[(size_t)k * n];
-      cd s = 0.0;
-      for (int i = j; i < n; ++i) s += std::conj(h[i - j]) * ck[i];
-      s *= 2.0 / hn2;
-      for (int i = j; i < n; ++i) ck[i] -= s * h[i - j];
+    for (int k = j + 1; k < v; ++k) {
+      double* c = &A[(size_t)k * nr];
+      const double f = 2.0 * dot(h, c, j) / hn2;
+      for (int i = j; i < nr; ++i) c[i] -= f * h[i];
     }
-    cd s = 0.0;
-    for (int i = j; i < n; ++i) s += std::conj(h[i - j]) * b[i];
-    s *= 2.0 / hn2;
-    for (int i = j; i < n; ++i) b[i] -= s * h[i - j];
+    const double f = 2.0 * dot(h, bb.data(), j) / hn2;
+    for (int i = j; i < nr; ++i) bb[i] -= f * h[i];
   }
-  std::vector<cd> x(v);
-  for (int j = v - 1; j >= 0; --j) {
-    cd s = b[j];
-    for (int k = j + 1; k < v; ++k) s -= M[(size_t)k * n + j] * x[k];
-    x[j] = s / M[(size_t)j * n + j];
+  wout.assign(v, 0.0);
+  for (int j = std::min(v, nr) - 1; j >= 0; --j) {
+    double s = bb[j];
+    for (int k = j + 1; k < v; ++k) s -= A[(size_t)k * nr + j] * wout[k];
+    wout[j] = diag[j] != 0.0 ? s / diag[j] : 0.0;
   }
-  double mi = 0.0;
-  wout.resize(v);
-  for (int j = 0; j < v; ++j) {
-    wout[j] = x[j].real();
-    mi = std::max(mi, std::fabs(x[j].imag()));
-  }
-  return mi;
+  return 0.0;  // the minimiser is real by construction
 }
 
 // ---------------------------------------------------------------------------
