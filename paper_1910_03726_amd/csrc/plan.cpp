@@ -250,12 +250,7 @@ int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, i
     NL = whole[0].NL;
     Wbucket = Wb;
     dense.resize(Wb, 0.0);
-    if (hipMalloc(&d_taps, dense.size() * sizeof(double)) != hipSuccess) return MGRIT_ENOMEM;
-    bytes += dense.size() * sizeof(double);
-    if (hipMemcpy(d_taps, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice) !=
-        hipSuccess)
-      return MGRIT_EHIP;
-    return MGRIT_OK;
+    return upload((void**)&d_taps, dense.data(), dense.size() * sizeof(double));
   }
   // generic LDS kernel: state of 2 n_x values in LDS
   if ((size_t)2 * nx * sizeof(double) > 160 * 1024) {
@@ -278,15 +273,9 @@ int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, i
     }
   ntaps = (int)off.size();
   omin = 0;
-  if (hipMalloc(&d_taps, std::max<size_t>(1, w.size()) * sizeof(double)) != hipSuccess ||
-      hipMalloc(&d_off, std::max<size_t>(1, off.size()) * sizeof(int)) != hipSuccess)
-    return MGRIT_ENOMEM;
-  bytes += w.size() * (sizeof(double) + sizeof(int));
-  if (hipMemcpy(d_taps, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) !=
-          hipSuccess)
-    return MGRIT_EHIP;
+  int rc = upload((void**)&d_taps, w.data(), w.size() * sizeof(double));
+  if (!rc) rc = upload((void**)&d_off, off.data(), off.size() * sizeof(int));
+  if (rc) return rc;
   for (int p = 0; p < 2; ++p)
     if (shmem[p] > kernel_info(fn[p]).max_lds) {
       err = "n_x too large for the generic relaxation kernel";
@@ -334,17 +323,24 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
       err = "n_x too large for the SDIRK kernel's LDS staging";
       return MGRIT_EINVAL;
     }
-  if (hipMalloc(&d_sdirk, sizeof(SdirkDev)) != hipSuccess) return MGRIT_ENOMEM;
-  bytes += sizeof(SdirkDev);
-  if (hipMemcpy(d_sdirk, &sd, sizeof(SdirkDev), hipMemcpyHostToDevice) != hipSuccess)
+  return upload(&d_sdirk, &sd, sizeof(SdirkDev));
+}
+
+int OpDesc::upload(void** d, const void* h, size_t b) {
+  if (dev_alloc(d, std::max<size_t>(b, 8), stream) != MGRIT_OK) return MGRIT_ENOMEM;
+  bytes += b;
+  if (b == 0) return MGRIT_OK;
+  staged.emplace_back((const char*)h, (const char*)h + b);
+  if (hipMemcpyAsync(*d, staged.back().data(), b, hipMemcpyHostToDevice, stream) != hipSuccess)
     return MGRIT_EHIP;
   return MGRIT_OK;
 }
 
 void OpDesc::release() {
-  if (d_taps) (void)hipFree(d_taps);
-  if (d_off) (void)hipFree(d_off);
-  if (d_sdirk) (void)hipFree(d_sdirk);
+  dev_free(d_taps, stream);
+  dev_free(d_off, stream);
+  dev_free(d_sdirk, stream);
+  staged.clear();
   d_taps = nullptr;
   d_off = nullptr;
   d_sdirk = nullptr;
@@ -619,6 +615,86 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
 
 using namespace mgr;
 
+namespace mgr {
+
+// The current device must be a gfx950; the answer is cached per device.
+// Stream-ordered allocation is used where the device's default pool exists;
+// the pool is told to keep freed blocks (plans come and go at a high rate).
+static std::atomic<int> g_known[64];  // 0 unknown, 1 gfx950, 2 other
+static std::atomic<int> g_pooled[64];
+
+static int check_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MGRIT_ENODEV;
+  if (dev < 64 && g_known[dev].load() != 0)
+    return g_known[dev].load() == 1 ? MGRIT_OK : MGRIT_ENODEV;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MGRIT_ENODEV;
+  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+  int pools = 0;
+  hipMemPool_t pool = nullptr;
+  if (ok && hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, dev) ==
+                hipSuccess &&
+      pools && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t keep = ~0ull;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess &&
+        dev < 64)
+      g_pooled[dev].store(1);
+  }
+  (void)hipGetLastError();
+  if (dev < 64) g_known[dev].store(ok ? 1 : 2);
+  return ok ? MGRIT_OK : MGRIT_ENODEV;
+}
+
+static bool pooled() {
+  int dev = 0;
+  return hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_pooled[dev].load() == 1;
+}
+
+int dev_alloc(void** p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  const hipError_t e = (s && pooled()) ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return MGRIT_ENOMEM;
+  }
+  return MGRIT_OK;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (s && pooled()) (void)hipFreeAsync(p, s);
+  else (void)hipFree(p);
+}
+
+// Pinned host words that receive residual norms, one per plan.  They come
+// from slabs kept until the process ends: releasing pinned memory waits for
+// the whole device, which would stall every other stream at each plan's end.
+std::mutex g_word_mu;
+std::vector<double*> g_free_words;
+
+static double* take_host_word() {
+  std::lock_guard<std::mutex> lk(g_word_mu);
+  if (g_free_words.empty()) {
+    constexpr int kSlab = 1024;
+    double* slab = nullptr;
+    if (hipHostMalloc((void**)&slab, kSlab * sizeof(double)) != hipSuccess) return nullptr;
+    for (int i = kSlab - 1; i >= 0; --i) g_free_words.push_back(slab + i);
+  }
+  double* w = g_free_words.back();
+  g_free_words.pop_back();
+  return w;
+}
+
+static void give_host_word(double* w) {
+  if (!w) return;
+  std::lock_guard<std::mutex> lk(g_word_mu);
+  g_free_words.push_back(w);
+}
+
+}  // namespace mgr
+
 // ---------------------------------------------------------------------------
 // C-ABI
 // ---------------------------------------------------------------------------
@@ -695,18 +771,6 @@ int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels, int ru
   return rc;
 }
 
-// The current device must be a gfx950; the answer is cached per device.
-static int check_device() {
-  static std::atomic<int> known[64];  // 0 unknown, 1 gfx950, 2 other
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MGRIT_ENODEV;
-  if (dev < 64 && known[dev].load() != 0) return known[dev].load() == 1 ? MGRIT_OK : MGRIT_ENODEV;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MGRIT_ENODEV;
-  const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-  if (dev < 64) known[dev].store(ok ? 1 : 2);
-  return ok ? MGRIT_OK : MGRIT_ENODEV;
-}
 
 int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
                       int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
@@ -754,6 +818,7 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
     long long n = nt;
     for (int l = 0; l < levels; ++l) {
       Level& L = P->lev[l];
+      L.op.stream = L.seq.stream = P->stream;
       L.n = (int)n;
       L.nc = (l < levels - 1) ? (int)(n / m) : 0;
       if (l == 0) {
@@ -777,7 +842,7 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
     // device buffers
     auto alloc = [&](double** p, long long rows) {
       size_t b = (size_t)rows * nx * sizeof(double);
-      if (hipMalloc((void**)p, b) != hipSuccess) return false;
+      if (dev_alloc((void**)p, b, P->stream) != MGRIT_OK) return false;
       P->bytes += b;
       return true;
     };
@@ -792,10 +857,10 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
       if (l < levels - 1 && (!alloc(&L.V, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
         return fail(MGRIT_ENOMEM);
     }
-    if (hipMalloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double)) !=
-            hipSuccess ||
-        hipMalloc((void**)&P->d_norm, sizeof(double)) != hipSuccess ||
-        hipHostMalloc((void**)&P->h_norm, sizeof(double)) != hipSuccess)
+    if (dev_alloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double),
+                  P->stream) != MGRIT_OK ||
+        dev_alloc((void**)&P->d_norm, sizeof(double), P->stream) != MGRIT_OK ||
+        !(P->h_norm = take_host_word()))
       return fail(MGRIT_ENOMEM);
     P->bytes += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);
     std::string d;
@@ -809,6 +874,12 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
   } catch (...) {
     return fail(MGRIT_ENOMEM);
   }
+  // allocations and uploads were queued on the plan's stream
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(MGRIT_EHIP);
+  for (auto& L : P->lev) {
+    L.op.staged.clear();
+    L.seq.staged.clear();
+  }
   *out = reinterpret_cast<mgrit_plan_t>(P);
   return MGRIT_OK;
 }
@@ -821,13 +892,12 @@ void mgrit_destroy(mgrit_plan_t plan) {
   for (auto& L : P->lev) {
     L.op.release();
     L.seq.release();
-    if (L.X) (void)hipFree(L.X);
-    if (L.V) (void)hipFree(L.V);
-    if (L.R) (void)hipFree(L.R);
+    dev_free(L.X, P->stream);
+    dev_free(L.V, P->stream);
+    dev_free(L.R, P->stream);
   }
-  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm})
-    if (p) (void)hipFree(p);
-  if (P->h_norm) (void)hipHostFree(P->h_norm);
+  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm}) dev_free(p, P->stream);
+  give_host_word(P->h_norm);
   for (auto& p : P->pending) {
     (void)hipEventDestroy(p.e0);
     (void)hipEventDestroy(p.e1);

@@ -18,6 +18,13 @@ enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
 // Fine-level residual passes write one partial sum per interval and tile.
 constexpr int kMaxFineTiles = 16;
 
+// Device memory of a plan.  On a stream, allocation and release are ordered
+// on that stream (the device's default memory pool, which keeps freed blocks
+// for reuse), so that building or dropping a plan never waits for work queued
+// on other streams; on the null stream plain hipMalloc / hipFree.
+int dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
 // One launch shape of the stencil kernel: `tiles` workgroups per interval,
 // each of NL lanes x K points, writing `tile` points.  A tiled shape
 // (tiles > 1) is valid for passes of at most `max_steps` steps (the tile's
@@ -45,6 +52,12 @@ struct OpDesc {
   int* d_off = nullptr;
   void* d_sdirk = nullptr;
   size_t bytes = 0;
+  hipStream_t stream = nullptr;         // allocation and upload stream
+  std::vector<std::vector<char>> staged;  // host sources of pending uploads
+
+  // allocate `b` device bytes at *d and queue the upload of `h` (copied to
+  // `staged`, dropped once the stream has drained)
+  int upload(void** d, const void* h, size_t b);
 
   // steps: fine steps of one relaxation pass (m), or of the whole sweep
   // (seq); nblk: workgroup rows of a pass (intervals); max_tiles: bound on

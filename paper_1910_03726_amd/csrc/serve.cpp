@@ -20,6 +20,7 @@
 
 #include "../../include/mgrit.h"
 #include "../../include/mgrit_serve.h"
+#include "plan.h"
 #include "setup.h"
 
 namespace mgr {
@@ -144,7 +145,9 @@ struct Server {
   void slot_loop() {
     (void)hipSetDevice(device);
     hipStream_t stream = nullptr;
-    if (hipStreamCreate(&stream) != hipSuccess) stream = nullptr;
+    // non-blocking: no implicit ordering against the null stream, so one
+    // slot's setup never waits for the kernels of the others
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
     for (;;) {
       std::shared_ptr<Req> q;
       {
@@ -182,7 +185,7 @@ struct Server {
     if (rc != MGRIT_OK) return;
     double* dev = nullptr;
     size_t row = (size_t)r.nx * sizeof(double);
-    if (hipMalloc((void**)&dev, 2 * row) != hipSuccess) {
+    if (mgr::dev_alloc((void**)&dev, 2 * row, stream) != MGRIT_OK) {
       q.res.status = MGRIT_ENOMEM;
       mgrit_destroy(plan);
       return;
@@ -208,7 +211,7 @@ struct Server {
           hipStreamSynchronize(stream) != hipSuccess)
         q.res.status = MGRIT_EHIP;
     }
-    (void)hipFree(dev);
+    mgr::dev_free(dev, stream);
     mgrit_destroy(plan);
   }
 };
@@ -350,6 +353,11 @@ void mgrit_server_destroy(mgrit_server_t server) {
   S->cv.notify_all();
   for (auto& t : S->workers)
     if (t.joinable()) t.join();
+  // hand the blocks the plans released back to the device
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess)
+    (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
   delete S;
 }
 
