@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -99,7 +100,28 @@ static double stencil_time_us(int nwg, int NL, int K, int Wb, int S, int occ) {
   return rounds * (S * step + 4800.0) * clk_us + 1.5;
 }
 
+// Resident workgroups per CU, cached per (kernel, lanes, LDS bytes): the
+// planner asks for hundreds of candidate shapes per plan.
 static int occupancy(KernelFn fn, int NL, size_t lds) {
+  struct Key {
+    const void* fn;
+    int NL;
+    size_t lds;
+    bool operator==(const Key& o) const { return fn == o.fn && NL == o.NL && lds == o.lds; }
+  };
+  struct Hash {
+    size_t operator()(const Key& k) const {
+      return std::hash<const void*>()(k.fn) ^ (std::hash<size_t>()(k.lds * 1024 + k.NL) << 1);
+    }
+  };
+  static std::mutex mu;
+  static std::unordered_map<Key, int, Hash> cache;
+  const Key key{(const void*)fn, NL, lds};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, NL, lds) !=
       hipSuccess) {
@@ -107,6 +129,8 @@ static int occupancy(KernelFn fn, int NL, size_t lds) {
     nb = 1;
   }
   if (nb < 1) nb = 1;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = nb;
   return nb;
 }
 
@@ -327,7 +351,7 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
 }
 
 int OpDesc::upload(void** d, const void* h, size_t b) {
-  if (dev_alloc(d, std::max<size_t>(b, 8), stream) != MGRIT_OK) return MGRIT_ENOMEM;
+  if (dev_alloc(d, b) != MGRIT_OK) return MGRIT_ENOMEM;
   bytes += b;
   if (b == 0) return MGRIT_OK;
   staged.emplace_back((const char*)h, (const char*)h + b);
@@ -337,9 +361,9 @@ int OpDesc::upload(void** d, const void* h, size_t b) {
 }
 
 void OpDesc::release() {
-  dev_free(d_taps, stream);
-  dev_free(d_off, stream);
-  dev_free(d_sdirk, stream);
+  dev_free(d_taps);
+  dev_free(d_off);
+  dev_free(d_sdirk);
   staged.clear();
   d_taps = nullptr;
   d_off = nullptr;
@@ -618,54 +642,98 @@ using namespace mgr;
 namespace mgr {
 
 // The current device must be a gfx950; the answer is cached per device.
-// Stream-ordered allocation is used where the device's default pool exists;
-// the pool is told to keep freed blocks (plans come and go at a high rate).
-static std::atomic<int> g_known[64];  // 0 unknown, 1 gfx950, 2 other
-static std::atomic<int> g_pooled[64];
-
 static int check_device() {
+  static std::atomic<int> known[64];  // 0 unknown, 1 gfx950, 2 other
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) return MGRIT_ENODEV;
-  if (dev < 64 && g_known[dev].load() != 0)
-    return g_known[dev].load() == 1 ? MGRIT_OK : MGRIT_ENODEV;
+  if (dev < 64 && known[dev].load() != 0) return known[dev].load() == 1 ? MGRIT_OK : MGRIT_ENODEV;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return MGRIT_ENODEV;
   const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
-  int pools = 0;
-  hipMemPool_t pool = nullptr;
-  if (ok && hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, dev) ==
-                hipSuccess &&
-      pools && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t keep = ~0ull;
-    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess &&
-        dev < 64)
-      g_pooled[dev].store(1);
-  }
-  (void)hipGetLastError();
-  if (dev < 64) g_known[dev].store(ok ? 1 : 2);
+  if (dev < 64) known[dev].store(ok ? 1 : 2);
   return ok ? MGRIT_OK : MGRIT_ENODEV;
 }
 
-static bool pooled() {
-  int dev = 0;
-  return hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_pooled[dev].load() == 1;
-}
+// Device blocks of plans.  A released block is kept and handed to a later
+// request of the same size class (four classes per power of two, so at most
+// 25 % above the bytes asked for) on the same device: giving a block back to
+// the driver costs up to several hundred microseconds and taking it again
+// tens, which a server that builds and drops a plan per request would pay on
+// every array.  Callers release a block only when no queued work uses it
+// any more.  At most kCacheCap bytes are kept; dev_trim() frees them all.
+namespace {
+constexpr size_t kCacheCap = (size_t)16 << 30;
+std::mutex g_blk_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_blk_free;
+std::unordered_map<void*, std::pair<int, size_t>> g_blk_live;
+size_t g_blk_cached = 0;
 
-int dev_alloc(void** p, size_t bytes, hipStream_t s) {
+size_t size_class(size_t b) {
+  b = std::max<size_t>(b, 4096);
+  int p = 63 - __builtin_clzll((unsigned long long)b);
+  const size_t step = (size_t)1 << (p - 2);
+  return (b + step - 1) / step * step;
+}
+}  // namespace
+
+int dev_alloc(void** p, size_t bytes) {
   *p = nullptr;
-  const hipError_t e = (s && pooled()) ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return MGRIT_ENOMEM;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MGRIT_ENODEV;
+  const size_t c = size_class(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    auto it = g_blk_free.find({dev, c});
+    if (it != g_blk_free.end() && !it->second.empty()) {
+      *p = it->second.back();
+      it->second.pop_back();
+      g_blk_cached -= c;
+      g_blk_live[*p] = {dev, c};
+      return MGRIT_OK;
+    }
   }
+  if (hipMalloc(p, c) != hipSuccess) {
+    (void)hipGetLastError();
+    dev_trim();
+    if (hipMalloc(p, c) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return MGRIT_ENOMEM;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_blk_mu);
+  g_blk_live[*p] = {dev, c};
   return MGRIT_OK;
 }
 
-void dev_free(void* p, hipStream_t s) {
+void dev_free(void* p) {
   if (!p) return;
-  if (s && pooled()) (void)hipFreeAsync(p, s);
-  else (void)hipFree(p);
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    auto it = g_blk_live.find(p);
+    if (it != g_blk_live.end()) {
+      const auto key = it->second;
+      g_blk_live.erase(it);
+      if (g_blk_cached + key.second <= kCacheCap) {
+        g_blk_free[key].push_back(p);
+        g_blk_cached += key.second;
+        return;
+      }
+    }
+  }
+  (void)hipFree(p);
+}
+
+void dev_trim() {
+  std::vector<void*> all;
+  {
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    for (auto& kv : g_blk_free)
+      for (void* q : kv.second) all.push_back(q);
+    g_blk_free.clear();
+    g_blk_cached = 0;
+  }
+  for (void* q : all) (void)hipFree(q);
 }
 
 // Pinned host words that receive residual norms, one per plan.  They come
@@ -842,7 +910,7 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
     // device buffers
     auto alloc = [&](double** p, long long rows) {
       size_t b = (size_t)rows * nx * sizeof(double);
-      if (dev_alloc((void**)p, b, P->stream) != MGRIT_OK) return false;
+      if (dev_alloc((void**)p, b) != MGRIT_OK) return false;
       P->bytes += b;
       return true;
     };
@@ -857,9 +925,9 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
       if (l < levels - 1 && (!alloc(&L.V, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
         return fail(MGRIT_ENOMEM);
     }
-    if (dev_alloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double),
-                  P->stream) != MGRIT_OK ||
-        dev_alloc((void**)&P->d_norm, sizeof(double), P->stream) != MGRIT_OK ||
+    if (dev_alloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double)) !=
+            MGRIT_OK ||
+        dev_alloc((void**)&P->d_norm, sizeof(double)) != MGRIT_OK ||
         !(P->h_norm = take_host_word()))
       return fail(MGRIT_ENOMEM);
     P->bytes += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);
@@ -892,11 +960,11 @@ void mgrit_destroy(mgrit_plan_t plan) {
   for (auto& L : P->lev) {
     L.op.release();
     L.seq.release();
-    dev_free(L.X, P->stream);
-    dev_free(L.V, P->stream);
-    dev_free(L.R, P->stream);
+    dev_free(L.X);
+    dev_free(L.V);
+    dev_free(L.R);
   }
-  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm}) dev_free(p, P->stream);
+  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm}) dev_free(p);
   give_host_word(P->h_norm);
   for (auto& p : P->pending) {
     (void)hipEventDestroy(p.e0);

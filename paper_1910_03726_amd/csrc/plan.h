@@ -18,12 +18,11 @@ enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
 // Fine-level residual passes write one partial sum per interval and tile.
 constexpr int kMaxFineTiles = 16;
 
-// Device memory of a plan.  On a stream, allocation and release are ordered
-// on that stream (the device's default memory pool, which keeps freed blocks
-// for reuse), so that building or dropping a plan never waits for work queued
-// on other streams; on the null stream plain hipMalloc / hipFree.
-int dev_alloc(void** p, size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
+// Device memory of plans, from a per-device cache of released blocks (see
+// plan.cpp); dev_free only once no queued work uses the block.
+int dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+void dev_trim();
 
 // One launch shape of the stencil kernel: `tiles` workgroups per interval,
 // each of NL lanes x K points, writing `tile` points.  A tiled shape

@@ -185,7 +185,7 @@ struct Server {
     if (rc != MGRIT_OK) return;
     double* dev = nullptr;
     size_t row = (size_t)r.nx * sizeof(double);
-    if (mgr::dev_alloc((void**)&dev, 2 * row, stream) != MGRIT_OK) {
+    if (mgr::dev_alloc((void**)&dev, 2 * row) != MGRIT_OK) {
       q.res.status = MGRIT_ENOMEM;
       mgrit_destroy(plan);
       return;
@@ -211,7 +211,8 @@ struct Server {
           hipStreamSynchronize(stream) != hipSuccess)
         q.res.status = MGRIT_EHIP;
     }
-    mgr::dev_free(dev, stream);
+    (void)hipStreamSynchronize(stream);
+    mgr::dev_free(dev);
     mgrit_destroy(plan);
   }
 };
@@ -353,11 +354,8 @@ void mgrit_server_destroy(mgrit_server_t server) {
   S->cv.notify_all();
   for (auto& t : S->workers)
     if (t.joinable()) t.join();
-  // hand the blocks the plans released back to the device
-  hipMemPool_t pool = nullptr;
-  if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess)
-    (void)hipMemPoolTrimTo(pool, 0);
-  (void)hipGetLastError();
+  // hand the blocks the plans released back to the driver
+  mgr::dev_trim();
   delete S;
 }
 
