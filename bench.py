@@ -200,7 +200,7 @@ def _serve_run(reqs, u0s, arrivals, slots, setup_threads, budget):
     return res, makespan, st
 
 
-def serving(n, torch, slots=8, setup_threads=16, budget_gib=128):
+def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
     """The serving mix: saturated throughput, then Poisson arrivals at 80% of
     it (p50/p99 latency); the plain FP64 per-solve form on a 10% sample."""
     import numpy as np
