@@ -102,6 +102,8 @@ typedef struct {
     int fine_passes_fp32;  /* fine-level relaxation passes run in FP32        */
     double final_residual; /* sqrt(dx dt sum r^2) of the returned iterate     */
     double solve_ms;       /* wall time of the solve (host clock)             */
+    long long batched_launches; /* mgrit_solve_batch: relaxation launches of
+                              this plan that ran merged with other plans'   */
 } mgrit_stats;
 
 /* Per-kernel-class GPU time, collected with HIP events when profiling is on. */
@@ -193,6 +195,28 @@ int mgrit_solve(mgrit_plan_t plan, const double* u0_dev,
                 const double* uinit_dev, double tol, int maxit,
                 double* u_out_dev, int out_kind, double* res_hist_host,
                 int* iters_out);
+
+/* n solves at once (the same iteration as mgrit_solve for each, Sec. 2.2
+ * and 4.4), stepped together on the plans' common stream: at every pass
+ * the relaxation launches of plans with the same kernel and launch shape
+ * (same n_x, scheme, level sizes and precision; any Courant number, Psi,
+ * u0, tolerance) run as one launch over their concatenated grids, so that
+ * small solves fill the device together.  Each result equals that of
+ * mgrit_solve on the same plan and inputs, bit for bit.
+ *   plans:   n distinct plans created on the same hip_stream (else
+ *            MGRIT_EINVAL, nothing run).
+ *   u0, tol, maxit, out_kind, status: n entries each; uinit, u_out, hist
+ *            may be NULL (all entries NULL), else n entries, each as in
+ *            mgrit_solve; iters may be NULL, else n entries.
+ *   status:  per plan, what mgrit_solve would have returned.
+ * Returns MGRIT_OK once every solve has ended (see status), MGRIT_EINVAL
+ * for invalid arguments, or the first HIP error.  Synchronous. */
+int mgrit_solve_batch(int n, const mgrit_plan_t* plans,
+                      const double* const* u0_dev,
+                      const double* const* uinit_dev, const double* tol,
+                      const int* maxit, double* const* u_out_dev,
+                      const int* out_kind, double* const* res_hist_host,
+                      int* iters_out, int* status);
 
 /* out[b] = Phi^k in[b] for b = 0..batch-1, rows of n_x values (device,
  * row-major, in and out may not overlap).  The fine stepper of the plan in

@@ -33,6 +33,7 @@ def _jobs():
     objs.append(("g++", os.path.join(CSRC, "setup.cpp"), "setup.o", []))
     objs.append((HIPCC, os.path.join(CSRC, "plan.cpp"), "plan.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "serve.cpp"), "serve.o", ["-x", "hip"]))
+    objs.append((HIPCC, os.path.join(CSRC, "solve.cpp"), "solve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
     for prec in (0, 1):
         objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),

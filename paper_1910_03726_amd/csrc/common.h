@@ -61,6 +61,17 @@ struct RelaxArgs {
                            // rows staged in LDS before the first step
 };
 
+// Several relaxation launches of the same kernel and launch shape merged
+// into one grid (requests served together): member i owns blocks
+// start[i] .. start[i+1]-1 (start[0] = 0) and runs with a[i] as if it had
+// been launched alone.
+constexpr int kMaxBatch = 8;
+struct BatchArgs {
+  RelaxArgs a[kMaxBatch];
+  int start[kMaxBatch];
+  int n;  // members, 1..kMaxBatch
+};
+
 // One factor of a cyclic banded stage solve: a linear recurrence of order
 // <= 2 run forward (dir = +1: y_i = x_i + a1 y_{i-1} + a2 y_{i-2}) or
 // backward (dir = -1: y_i = x_i + a1 y_{i+1} + a2 y_{i+2}), periodic in i.

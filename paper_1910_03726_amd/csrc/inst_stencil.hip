@@ -22,9 +22,11 @@ typedef float StateT;
 
 void MGR_CAT3(register_stencil, MGR_PREC, MGR_K)(KernelTable& t) {
   const int ki = k_index(MGR_K);
-#define MGR_X(W)                                                              \
-  t.stencil[MGR_PREC][ki][width_index(W)][0] = &k_stencil<StateT, MGR_K, W, false>; \
-  t.stencil[MGR_PREC][ki][width_index(W)][1] = &k_stencil<StateT, MGR_K, W, true>;
+#define MGR_X(W)                                                                \
+  t.stencil[MGR_PREC][ki][width_index(W)][0] = &k_stencil<StateT, MGR_K, W, false>;   \
+  t.stencil[MGR_PREC][ki][width_index(W)][1] = &k_stencil<StateT, MGR_K, W, true>;    \
+  t.stencil_b[MGR_PREC][ki][width_index(W)][0] = &k_stencil_b<StateT, MGR_K, W, false>; \
+  t.stencil_b[MGR_PREC][ki][width_index(W)][1] = &k_stencil_b<StateT, MGR_K, W, true>;
   MGR_STENCIL_WIDTHS(MGR_X)
 #undef MGR_X
 }

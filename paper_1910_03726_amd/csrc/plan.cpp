@@ -151,7 +151,8 @@ static bool finish_shape(StencilShape& sh, int E, int Wb, bool io) {
   if (sh.shmem[0] > 160 * 1024) return false;
   for (int q = 0; q < 2; ++q) {
     sh.fn[q] = kt.stencil[q][ki][wi][io ? 1 : 0];
-    if (!sh.fn[q]) return false;
+    sh.bfn[q] = kt.stencil_b[q][ki][wi][io ? 1 : 0];
+    if (!sh.fn[q] || !sh.bfn[q]) return false;
   }
   return true;
 }
@@ -286,6 +287,8 @@ int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, i
   NL = 256;
   fn[0] = kt.generic[0];
   fn[1] = kt.generic[1];
+  bfn[0] = kt.generic_b[0];
+  bfn[1] = kt.generic_b[1];
   shmem[0] = (size_t)2 * nx * sizeof(double);
   shmem[1] = (size_t)2 * nx * sizeof(float);
   std::vector<int> off;
@@ -340,6 +343,8 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   kind = OP_SDIRK;
   fn[0] = kt.sdirk[0][sdirk_k_index(K)][si];
   fn[1] = kt.sdirk[1][sdirk_k_index(K)][si];
+  bfn[0] = kt.sdirk_b[0][sdirk_k_index(K)][si];
+  bfn[1] = kt.sdirk_b[1][sdirk_k_index(K)][si];
   shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
   nnz = 0;
   for (int p = 0; p < 2; ++p)
@@ -418,6 +423,7 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
   const bool io = a.rhs_mode == RHS_EVERY || a.mode == MODE_F;
   RelaxArgs args = a;
   KernelFn fn = op.fn[prec];
+  BatchFn bfn = op.bfn[prec];
   int nl = op.NL;
   size_t lds = op.shmem[prec];
   long long blocks = grid;
@@ -427,6 +433,7 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
     if (op.tiled[io].tiles > 1 && a.m >= 1 && a.m <= op.tiled[io].max_steps)
       sh = &op.tiled[io];
     fn = sh->fn[prec];
+    bfn = sh->bfn[prec];
     nl = sh->NL;
     lds = sh->shmem[prec];
     args.tile = sh->tile;
@@ -440,6 +447,10 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
     parts = (int)blocks;
   }
   if (!fn || blocks < 1 || blocks > 0x7fffffffLL) return MGRIT_EINVAL;
+  if (batch) {
+    batch->pending.push_back({fn, bfn, nl, lds, blocks, args, this});
+    return MGRIT_OK;
+  }
   void* kargs[] = {&args};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (profiling) {
@@ -549,72 +560,82 @@ int Plan::copy_cpoints(int l, int prec, const double* in, long long in_stride,
 // Coarsest level: x^0 = g^0 = 0, x^{n+1} = Phi_L x^n + g^{n+1}, all points.
 // Always FP64 (the sequential coarse solve stays FP64 in every precision).
 // The sweep runs in launches of op.seq_chunk steps, each starting from the
-// last row the one before stored.
-int Plan::sequential(const double* g) {
+// last row the one before stored; this is the launch from step s0.
+int Plan::sequential_chunk(int s0, const double* g, bool* last) {
   Level& L = lev.back();
   const OpDesc& op = L.seq;
   const int S = op.seq_chunk > 0 ? op.seq_chunk : L.n;
-  for (int s0 = 0; s0 < L.n; s0 += S) {
-    RelaxArgs a = base_args(*this, op);
-    if (s0 == 0) {
-      a.zero_in = 1;
-    } else {
-      a.in = L.X + (long long)s0 * nx;
-      a.skip_row0 = 1;
-    }
-    a.rhs = g + (long long)s0 * nx;
-    a.rhs_mode = RHS_EVERY;
-    a.mode = MODE_F;
-    a.m = std::min(S, L.n - s0);
-    a.nint = 1;
-    a.write_last = 1;
-    a.out = L.X + (long long)s0 * nx;
-    const int rc = launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
-    if (rc) return rc;
-  }
-  return MGRIT_OK;
-}
-
-int Plan::norm(const double* partial, int n, double& value) {
-  hipEvent_t e0 = nullptr;
-  mark_util(MGRIT_PROF_NORM, e0);
-  launch_norm_reduce(partial, n, scale * scale, d_norm, stream);
-  end_util(MGRIT_PROF_NORM, e0);
-  if (hipMemcpyAsync(h_norm, d_norm, sizeof(double), hipMemcpyDeviceToHost, stream) !=
-      hipSuccess)
-    return MGRIT_EHIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return MGRIT_EHIP;
-  value = *h_norm;
-  return MGRIT_OK;
-}
-
-// Solve level l's error system (rhs g, zero initial guess) into lev[l].X.
-int Plan::coarse_solve(int l, const double* g, int kind, int prec) {
-  if (l == (int)lev.size() - 1) return sequential(g);
-  int rc;
-  if (kind == MGRIT_CYCLE_F) {
-    if ((rc = cycle(l, g, true, MGRIT_CYCLE_F, prec))) return rc;
-    return cycle(l, g, false, MGRIT_CYCLE_V, prec);
-  }
-  return cycle(l, g, true, MGRIT_CYCLE_V, prec);
-}
-
-// One V- or F-cycle on level l >= 1 (Sec. 4.4): relax, residual, coarse
-// solve, correct + F-relax.  Guess: lev[l].X (all points) unless `zero`.
-int Plan::cycle(int l, const double* g, bool zero, int kind, int prec) {
-  Level& L = lev[l];
-  int rc;
-  const double* guess = zero ? nullptr : L.X;
-  if (relax_kind == MGRIT_RELAX_FCF) {
-    if ((rc = relax(l, prec, MODE_FC, guess, m, nullptr, g, RHS_EVERY, L.V, nullptr, m)))
-      return rc;
+  RelaxArgs a = base_args(*this, op);
+  if (s0 == 0) {
+    a.zero_in = 1;
   } else {
-    // F-relaxation only: v = u
-    if ((rc = copy_cpoints(l, prec, guess, m, nullptr, L.V))) return rc;
+    a.in = L.X + (long long)s0 * nx;
+    a.skip_row0 = 1;
   }
-  if ((rc = relax(l, prec, MODE_RES, L.V, 1, nullptr, g, RHS_EVERY, L.R, nullptr, m))) return rc;
-  if ((rc = coarse_solve(l + 1, L.R, kind, prec))) return rc;
-  return relax(l, prec, MODE_F, L.V, 1, lev[l + 1].X, g, RHS_EVERY, L.X, nullptr, m);
+  a.rhs = g + (long long)s0 * nx;
+  a.rhs_mode = RHS_EVERY;
+  a.mode = MODE_F;
+  a.m = std::min(S, L.n - s0);
+  a.nint = 1;
+  a.write_last = 1;
+  a.out = L.X + (long long)s0 * nx;
+  *last = s0 + S >= L.n;
+  return launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
+}
+
+int Batch::flush() {
+  const size_t n = pending.size();
+  std::vector<char> used(n, 0);
+  int rc = MGRIT_OK;
+  for (size_t i = 0; i < n && rc == MGRIT_OK; ++i) {
+    if (used[i]) continue;
+    const Entry& e = pending[i];
+    // members joining entry i: same kernel and shape, at most one entry per
+    // plan, and no earlier entry of their plan still waiting
+    std::vector<size_t> grp(1, i);
+    used[i] = 1;
+    for (size_t k = i + 1; k < n && grp.size() < (size_t)kMaxBatch && e.bfn; ++k) {
+      const Entry& f = pending[k];
+      if (used[k] || f.fn != e.fn || f.nl != e.nl || f.lds != e.lds) continue;
+      bool ok = true;
+      for (size_t q = i; q < k && ok; ++q)
+        if (pending[q].owner == f.owner && (!used[q] || std::find(grp.begin(), grp.end(), q) != grp.end()))
+          ok = false;
+      if (!ok) continue;
+      grp.push_back(k);
+      used[k] = 1;
+    }
+    hipError_t st;
+    if (grp.size() == 1) {
+      RelaxArgs args = e.args;
+      void* kargs[] = {&args};
+      st = hipLaunchKernel((const void*)e.fn, dim3((unsigned)e.blocks), dim3(e.nl), kargs, e.lds,
+                           stream);
+    } else {
+      BatchArgs b;
+      std::memset(&b, 0, sizeof b);
+      long long total = 0;
+      for (size_t q = 0; q < grp.size(); ++q) {
+        b.a[q] = pending[grp[q]].args;
+        b.start[q] = (int)total;
+        total += pending[grp[q]].blocks;
+        pending[grp[q]].owner->stats.batched_launches += 1;
+      }
+      b.n = (int)grp.size();
+      if (total > 0x7fffffffLL || kernel_info((KernelFn)e.bfn).max_lds < e.lds) {
+        rc = MGRIT_EINVAL;
+        break;
+      }
+      void* kargs[] = {&b};
+      st = hipLaunchKernel((const void*)e.bfn, dim3((unsigned)total), dim3(e.nl), kargs, e.lds,
+                           stream);
+      merged += (long long)grp.size();
+    }
+    if (st != hipSuccess) rc = MGRIT_EHIP;
+    ++launches;
+  }
+  pending.clear();
+  return rc;
 }
 
 }  // namespace mgr
@@ -1065,216 +1086,6 @@ int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
   a.out_off = 0;
   const int prec = P->precision == MGRIT_FP32_RELAX ? 1 : 0;
   return P->launch(op, prec, a, batch, MGRIT_PROF_RELAX_FINE);
-}
-
-// ---- the solve ---------------------------------------------------------
-static int finish_output(Plan* P, const double* C, double* u_out, int out_kind) {
-  const int nx = P->nx, nc = P->nt / P->m;
-  const size_t row = (size_t)nx * sizeof(double);
-  switch (out_kind) {
-    case MGRIT_OUT_NONE: return MGRIT_OK;
-    case MGRIT_OUT_FINAL:
-      return hipMemcpyAsync(u_out, C + (size_t)nc * nx, row, hipMemcpyDeviceToDevice,
-                            P->stream) == hipSuccess ? MGRIT_OK : MGRIT_EHIP;
-    case MGRIT_OUT_CPOINTS:
-      return hipMemcpyAsync(u_out, C, row * (nc + 1), hipMemcpyDeviceToDevice, P->stream) ==
-                     hipSuccess ? MGRIT_OK : MGRIT_EHIP;
-    case MGRIT_OUT_ALL:
-      // F-relaxation of the converged C-points on the fine level, in FP64
-      return P->relax(0, 0, MODE_F, C, 1, nullptr, nullptr, RHS_NONE, u_out, nullptr, P->m);
-    default: return MGRIT_EINVAL;
-  }
-}
-
-static int init_iterate(Plan* P, const double* u0, const double* uinit, double* dst) {
-  const int nx = P->nx, nc = P->nt / P->m;
-  const size_t row = (size_t)nx * sizeof(double);
-  if (uinit) {
-    if (hipMemcpyAsync(dst, uinit, row * (nc + 1), hipMemcpyDeviceToDevice, P->stream) !=
-        hipSuccess)
-      return MGRIT_EHIP;
-  } else {
-    launch_uniform_init(dst, nc + 1, nx, P->seed, P->stream);
-  }
-  return hipMemcpyAsync(dst, u0, row, hipMemcpyDeviceToDevice, P->stream) == hipSuccess
-             ? MGRIT_OK : MGRIT_EHIP;
-}
-
-static int solve_fp64(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
-                      double* u_out, int out_kind, double* hist, int* iters) {
-  const int nc = P->nt / P->m;
-  int rc = init_iterate(P, u0, uinit, P->Va);
-  if (rc) return rc;
-  double* cur = P->Va;
-  double* nxt = P->Vb;
-  const double* corr = nullptr;
-  int status = MGRIT_ENOTCONV;
-  int it = 0;
-  for (;; ++it) {
-    if (P->relax_kind == MGRIT_RELAX_FCF) {
-      if ((rc = P->relax(0, 0, MODE_FC, cur, 1, corr, nullptr, RHS_NONE, nxt, nullptr, P->m)))
-        return rc;
-      P->stats.fine_passes_fp64 += 1;
-    } else if ((rc = P->copy_cpoints(0, 0, cur, 1, corr, nxt))) {
-      return rc;
-    }
-    if ((rc = P->relax(0, 0, MODE_RES, nxt, 1, nullptr, nullptr, RHS_NONE, P->lev[0].R,
-                       P->partial, P->m)))
-      return rc;
-    P->stats.fine_passes_fp64 += 1;
-    double res = 0.0;
-    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
-    if (hist) hist[it] = res;
-    P->stats.final_residual = res;
-    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
-    if (res <= tol) { status = MGRIT_OK; break; }
-    if (it >= maxit) { status = MGRIT_ENOTCONV; break; }
-    if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 0))) return rc;
-    corr = P->lev[1].X;
-    std::swap(cur, nxt);
-  }
-  P->stats.iterations = it;
-  if (iters) *iters = it;
-  if ((rc = finish_output(P, nxt, u_out, out_kind))) return rc;
-  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
-  return status;
-}
-
-// FP32 relaxation as the correction of FP64 FCF-relaxed iterates.  With u
-// the current C-points (cur + corr), the FCF-relaxed iterate of the FP64
-// solver is v = FC(u) and its residual r_{j+1} = Phi^m v_j - v_{j+1}.
-// Writing v = u + d (d the C-relaxation update, d^0 = 0) gives exactly
-// r_{j+1} = Phi^m d_j, because Phi^m u_j = v_{j+1}: the second fine pass
-// acts only on the small update d and runs in FP32 with errors relative to
-// |d|, while the C-point iterate, its FC pass, the coarse correction and
-// the norms stay FP64.  Iteration by iteration this is the FP64 solver.
-static int solve_mixed(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
-                       double* u_out, int out_kind, double* hist, int* iters) {
-  int rc = init_iterate(P, u0, uinit, P->Va);
-  if (rc) return rc;
-  double* cur = P->Va;
-  double* nxt = P->Vb;
-  double* d = P->U;
-  const double* corr = nullptr;
-  int status = MGRIT_ENOTCONV;
-  int it = 0;
-  for (;; ++it) {
-    if ((rc = P->relax(0, 0, MODE_FC, cur, 1, corr, nullptr, RHS_NONE, nxt, nullptr, P->m, d)))
-      return rc;
-    P->stats.fine_passes_fp64 += 1;
-    if ((rc = P->relax(0, 1, MODE_FC, d, 1, nullptr, nullptr, RHS_NONE, P->lev[0].R,
-                       P->partial, P->m)))
-      return rc;
-    P->stats.fine_passes_fp32 += 1;
-    double res = 0.0;
-    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
-    if (hist) hist[it] = res;
-    P->stats.final_residual = res;
-    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
-    if (res <= tol) { status = MGRIT_OK; break; }
-    if (it >= maxit) { status = MGRIT_ENOTCONV; break; }
-    if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 0))) return rc;
-    corr = P->lev[1].X;
-    std::swap(cur, nxt);
-  }
-  P->stats.iterations = it;
-  P->stats.outer_iterations = it + 1;
-  if (iters) *iters = it;
-  if ((rc = finish_output(P, nxt, u_out, out_kind))) return rc;
-  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
-  return status;
-}
-
-// F-relaxation (Parareal) with FP32 relaxation, as FP64 iterative
-// refinement: the FP64 residual r of the iterate u, inner MGRIT cycles with
-// FP32 relaxation on the error system e^{j+1} = Phi^m e^j + r^{j+1}
-// (sequential coarse solve, residual subtraction and norms in FP64), then
-// u += e in FP64.
-static int solve_ir(Plan* P, const double* u0, const double* uinit, double tol, int maxit,
-                    double* u_out, int out_kind, double* hist, int* iters) {
-  const int nc = P->nt / P->m;
-  const long long cells = (long long)(nc + 1) * P->nx;
-  int rc = init_iterate(P, u0, uinit, P->U);
-  if (rc) return rc;
-  int status = MGRIT_ENOTCONV;
-  int outer = 0, inner_total = 0;
-  const double kInnerDrop = 1e-5;  // inner solve target relative to |r|
-  const int kInnerMax = 8;
-  for (;; ++outer) {
-    if ((rc = P->relax(0, 0, MODE_RES, P->U, 1, nullptr, nullptr, RHS_NONE, P->Rout,
-                       P->partial, P->m)))
-      return rc;
-    P->stats.fine_passes_fp64 += 1;
-    double res = 0.0;
-    if ((rc = P->norm(P->partial, P->parts, res))) return rc;
-    if (hist) hist[outer] = res;
-    P->stats.final_residual = res;
-    if (!std::isfinite(res)) { status = MGRIT_EDIVERGED; break; }
-    if (res <= tol) { status = MGRIT_OK; break; }
-    if (outer >= maxit) { status = MGRIT_ENOTCONV; break; }
-    double* cur = P->Va;
-    double* nxt = P->Vb;
-    const double* corr = nullptr;
-    double prev = res;
-    for (int k = 0;; ++k) {
-      if (P->relax_kind == MGRIT_RELAX_FCF) {
-        if ((rc = P->relax(0, 1, MODE_FC, k == 0 ? nullptr : cur, 1, corr, P->Rout,
-                           RHS_CPOINT, nxt, nullptr, P->m)))
-          return rc;
-        P->stats.fine_passes_fp32 += 1;
-      } else if ((rc = P->copy_cpoints(0, 1, k == 0 ? nullptr : cur, 1, corr, nxt))) {
-        return rc;
-      }
-      if ((rc = P->relax(0, 1, MODE_RES, nxt, 1, nullptr, P->Rout, RHS_CPOINT, P->lev[0].R,
-                         P->partial, P->m)))
-        return rc;
-      P->stats.fine_passes_fp32 += 1;
-      double rho = 0.0;
-      if ((rc = P->norm(P->partial, P->parts, rho))) return rc;
-      if (!std::isfinite(rho)) { status = MGRIT_EDIVERGED; break; }
-      // stop at the target, at the cap, or once a coarse correction stops
-      // halving the inner residual (FP32 rounding floor)
-      const bool done = rho <= kInnerDrop * res || k + 1 >= kInnerMax ||
-                        (k >= 1 && rho > 0.5 * prev);
-      prev = rho;
-      if (done) break;
-      if ((rc = P->coarse_solve(1, P->lev[0].R, P->cycle_kind, 1))) return rc;
-      ++inner_total;
-      corr = P->lev[1].X;
-      std::swap(cur, nxt);
-    }
-    if (status == MGRIT_EDIVERGED) break;
-    // u += e (the FCF-relaxed inner iterate whose residual was tested)
-    hipEvent_t e0 = nullptr;
-    P->mark_util(MGRIT_PROF_OTHER, e0);
-    launch_axpy(P->U, nxt, cells, P->stream);
-    P->end_util(MGRIT_PROF_OTHER, e0);
-    ++inner_total;
-  }
-  P->stats.iterations = inner_total;
-  P->stats.outer_iterations = outer;
-  if (iters) *iters = inner_total;
-  if ((rc = finish_output(P, P->U, u_out, out_kind))) return rc;
-  if (hipStreamSynchronize(P->stream) != hipSuccess) return MGRIT_EHIP;
-  return status;
-}
-
-int mgrit_solve(mgrit_plan_t plan, const double* u0, const double* uinit, double tol,
-                int maxit, double* u_out, int out_kind, double* hist, int* iters) {
-  if (!plan || !u0 || maxit < 0 || !(tol >= 0.0)) return MGRIT_EINVAL;
-  if (out_kind != MGRIT_OUT_NONE && !u_out) return MGRIT_EINVAL;
-  if (out_kind < MGRIT_OUT_NONE || out_kind > MGRIT_OUT_ALL) return MGRIT_EINVAL;
-  Plan* P = reinterpret_cast<Plan*>(plan);
-  std::memset(&P->stats, 0, sizeof P->stats);
-  auto t0 = std::chrono::steady_clock::now();
-  int rc = P->precision != MGRIT_FP32_RELAX
-               ? solve_fp64(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
-               : P->relax_kind == MGRIT_RELAX_FCF
-                     ? solve_mixed(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters)
-                     : solve_ir(P, u0, uinit, tol, maxit, u_out, out_kind, hist, iters);
-  auto t1 = std::chrono::steady_clock::now();
-  P->stats.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  return rc;
 }
 
 }  // extern "C"

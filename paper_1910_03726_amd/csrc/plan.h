@@ -33,6 +33,7 @@ struct StencilShape {
   int preload_rows = 0;                 // passes of <= this many steps stage
                                         // their right-hand side rows in LDS
   KernelFn fn[2] = {nullptr, nullptr};  // [FP64 state, FP32 state]
+  BatchFn bfn[2] = {nullptr, nullptr};  // their batched entries
   size_t shmem[2] = {0, 0};
   double est_us = 0.0;                  // planner's launch-time estimate
 };
@@ -41,6 +42,7 @@ struct StencilShape {
 struct OpDesc {
   int kind = OP_GENERIC;
   KernelFn fn[2] = {nullptr, nullptr};  // generic / SDIRK: [FP64 state, FP32 state]
+  BatchFn bfn[2] = {nullptr, nullptr};
   size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
   StencilShape whole[2], tiled[2];      // stencil: [no per-step IO, per-step IO]
   int seq_chunk = 0;                    // sequential sweeps: steps per launch
@@ -78,6 +80,29 @@ struct Level {
   double* R = nullptr;  // C-point residuals = right-hand side of level l+1
 };
 
+struct Plan;
+
+// Relaxation launches of several plans recorded on one stream and issued
+// together: launches of the same kernel, block size and LDS size (the same
+// pass of requests with the same shape) become one batched launch over the
+// concatenated grids; the others go out one by one.  A plan's launches keep
+// their order.
+struct Batch {
+  struct Entry {
+    KernelFn fn;
+    BatchFn bfn;
+    int nl;
+    size_t lds;
+    long long blocks;
+    RelaxArgs args;
+    Plan* owner;
+  };
+  hipStream_t stream = nullptr;
+  std::vector<Entry> pending;
+  long long launches = 0, merged = 0;  // kernels launched, entries merged into them
+  int flush();
+};
+
 struct ProfPending {
   int cls;
   hipEvent_t e0, e1;
@@ -103,6 +128,7 @@ struct Plan {
   std::vector<ProfPending> pending;
   std::vector<hipEvent_t> event_pool;
   int parts = 0;  // partial sums written by the last residual launch
+  Batch* batch = nullptr;  // set: relaxation launches are recorded there
 
   int launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int cls);
   hipEvent_t take_event();
@@ -114,10 +140,16 @@ struct Plan {
             double* partial, int steps, double* delta = nullptr);
   int copy_cpoints(int l, int prec, const double* in, long long in_stride,
                    const double* corr, double* out);
-  int sequential(const double* g);
-  int norm(const double* partial, int n, double& value);
-  int coarse_solve(int l, const double* g, int kind, int prec);
-  int cycle(int l, const double* g, bool zero, int kind, int prec);
+  // one launch of the coarsest level's sequential sweep (steps s0..), or 1
+  // in *last if it was the last one
+  int sequential_chunk(int s0, const double* g, bool* last);
 };
+
+// MGRIT solves of n plans on one stream, step by step together, with their
+// relaxation launches batched (solve.cpp); arguments as mgrit_solve, one
+// entry per plan, status[i] its return code.
+int solve_group(Plan* const* plans, int n, const double* const* u0, const double* const* uinit,
+                const double* tol, const int* maxit, double* const* u_out, const int* out_kind,
+                double* const* hist, int* iters, int* status);
 
 }  // namespace mgr

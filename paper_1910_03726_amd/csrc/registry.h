@@ -6,6 +6,7 @@
 namespace mgr {
 
 typedef void (*KernelFn)(RelaxArgs);
+typedef void (*BatchFn)(BatchArgs);  // the same kernel over a merged grid
 
 // Window widths W and chunk lengths K with a register-resident stencil
 // kernel; other shapes use the generic LDS kernel.
@@ -26,6 +27,10 @@ struct KernelTable {
   KernelFn stencil[2][kNumK][kNumWidths][2] = {};  // [prec][K][W][per-step IO]
   KernelFn sdirk[2][kNumSdirkK][kNumSdirkShapes] = {};
   KernelFn generic[2] = {};
+  // batched entries of the same kernels, same indices
+  BatchFn stencil_b[2][kNumK][kNumWidths][2] = {};
+  BatchFn sdirk_b[2][kNumSdirkK][kNumSdirkShapes] = {};
+  BatchFn generic_b[2] = {};
 };
 
 // Filled once on first use; prec 0 = FP64 state, 1 = FP32 state.

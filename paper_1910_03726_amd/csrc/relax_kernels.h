@@ -60,6 +60,17 @@ __device__ __forceinline__ void st_row(double* row, unsigned g, double v) {
 // also drains the prefetches and stores of the step before.
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// The member of a batched launch that this workgroup belongs to (its
+// arguments) and the workgroup's index within that member's own grid.
+__device__ __forceinline__ RelaxArgs batch_member(const BatchArgs& b, int& blk) {
+  const int x = (int)blockIdx.x;
+  int r = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxBatch; ++i) r += (i < b.n && x >= b.start[i]) ? 1 : 0;
+  blk = x - b.start[r];
+  return b.a[r];
+}
+
 // Deterministic block sum (fixed reduction order); result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* red) {
 #pragma unroll
@@ -255,8 +266,9 @@ struct Extent {
 // for coalesced access; residuals and their partial sum (one per
 // workgroup, at partial[j * tiles + c], i.e. at its block index).
 template <typename T, int K>
-__device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const Extent<K>& X, int eout, int sh,
-                                              const T (&x)[K], double* stg, double* red) {
+__device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, int blk, const Extent<K>& X,
+                                              int eout, int sh, const T (&x)[K], double* stg,
+                                              double* red) {
   if (a.mode != MODE_FC && a.mode != MODE_RES) return;
   const int nx = a.nx, NL = X.NL, lane = X.lane, E = X.E;
   __syncthreads();  // the image / staging area is no longer read
@@ -304,7 +316,7 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
   }
   if (a.partial) {
     const double s = block_sum(ss, red);
-    if (lane == 0) a.partial[blockIdx.x] = s;
+    if (lane == 0) a.partial[blk] = s;
   }
 }
 
@@ -339,7 +351,7 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, const E
 // values of T, M = W-1 rounded up to a multiple of K), then 2*H slots per
 // wavefront (first case only).
 template <typename T, int K, int W, bool IO>
-__global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
+__device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) {
   constexpr bool kShfl = (W - 1 <= K);
   constexpr int H = (W - 1 < K) ? (W - 1) : K;
   constexpr int HW = (W > 1) ? (W - 1) : 1;
@@ -347,7 +359,7 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   __shared__ double red[16];
 
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
-  const int c = (int)(blockIdx.x % (unsigned)a.tiles), j = (int)(blockIdx.x / (unsigned)a.tiles);
+  const int c = (int)((unsigned)blk % (unsigned)a.tiles), j = (int)((unsigned)blk / (unsigned)a.tiles);
   const int wave = lane >> 6, lw = lane & 63, nwave = NL >> 6;
   const int E = NL * K;
   const int t0 = c * a.tile, t1 = min(t0 + a.tile, nx);
@@ -594,18 +606,29 @@ __global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
   if (!every) run(std::false_type{}, std::false_type{});
   else if (preload) run(std::true_type{}, std::true_type{});
   else run(std::true_type{}, std::false_type{});
-  finish_extent<T, K>(a, j, X, eout, sh, x, stg, red);
+  finish_extent<T, K>(a, j, blk, X, eout, sh, x, stg, red);
+}
+
+template <typename T, int K, int W, bool IO>
+__global__ void __launch_bounds__(512) k_stencil(RelaxArgs a) {
+  stencil_body<T, K, W, IO>(a, (int)blockIdx.x);
+}
+
+template <typename T, int K, int W, bool IO>
+__global__ void __launch_bounds__(512) k_stencil_b(BatchArgs b) {
+  int blk;
+  const RelaxArgs a = batch_member(b, blk);
+  stencil_body<T, K, W, IO>(a, blk);
 }
 
 // ---------------------------------------------------------------------------
 // Generic: any n_x, any tap list (offsets in [0, n_x)); state in LDS
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_generic(RelaxArgs a) {
+__device__ __forceinline__ void generic_body(const RelaxArgs& a, const int j) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const int nx = a.nx, m = a.m, NT = blockDim.x, tid = threadIdx.x;
-  const int j = blockIdx.x;
   T* cur = reinterpret_cast<T*>(smem_raw);
   T* nxt = cur + nx;
   for (int p = tid; p < nx; p += NT) {
@@ -674,6 +697,18 @@ __global__ void __launch_bounds__(256) k_generic(RelaxArgs a) {
       if (tid == 0) a.partial[j] = s;
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_generic(RelaxArgs a) {
+  generic_body<T>(a, (int)blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_generic_b(BatchArgs b) {
+  int blk;
+  const RelaxArgs a = batch_member(b, blk);
+  generic_body<T>(a, blk);
 }
 
 }  // namespace mgr

@@ -104,13 +104,12 @@ __device__ __forceinline__ void rec_apply(T (&y)[K], const RecDev& f, const T (&
 
 // Dynamic LDS: the staging area (stage_doubles(n_x, K) doubles).
 template <typename T, int K, int S, int NF>
-__global__ void __launch_bounds__(512) k_sdirk(RelaxArgs a) {
+__device__ __forceinline__ void sdirk_body(const RelaxArgs& a, const int j) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ T scan[2][32];
   __shared__ double red[16];
   const SdirkDev* sd = reinterpret_cast<const SdirkDev*>(a.sdirk);
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
-  const int j = blockIdx.x;
   const Stager<K> St{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
 
   double v0[K];
@@ -180,6 +179,18 @@ __global__ void __launch_bounds__(512) k_sdirk(RelaxArgs a) {
       St.store(a.out + ((long long)j * m + s) * nx, 0, u);
   }
   finish<T, K>(a, j, St, 0, u, red);
+}
+
+template <typename T, int K, int S, int NF>
+__global__ void __launch_bounds__(512) k_sdirk(RelaxArgs a) {
+  sdirk_body<T, K, S, NF>(a, (int)blockIdx.x);
+}
+
+template <typename T, int K, int S, int NF>
+__global__ void __launch_bounds__(512) k_sdirk_b(BatchArgs b) {
+  int blk;
+  const RelaxArgs a = batch_member(b, blk);
+  sdirk_body<T, K, S, NF>(a, blk);
 }
 
 }  // namespace mgr

@@ -44,7 +44,8 @@ class Taps(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
                 ("fine_passes_fp64", ctypes.c_int), ("fine_passes_fp32", ctypes.c_int),
-                ("final_residual", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("final_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("batched_launches", ctypes.c_longlong)]
 
 
 class Profile(ctypes.Structure):
@@ -67,6 +68,43 @@ class Result(ctypes.Structure):
                 ("final_residual", ctypes.c_double), ("queue_ms", ctypes.c_double),
                 ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
                 ("hbm_bytes", ctypes.c_size_t), ("admit_seq", ctypes.c_longlong)]
+
+
+def solve_batch(plans, u0s, tol=1e-10, maxit=100, out="final"):
+    """mgrit_solve_batch: the solves of `plans` (same stream) stepped together,
+    launches of equal shape merged.  u0s: one device tensor of n_x values per
+    plan.  Returns one SolveResult per plan, in order."""
+    import torch
+    n = len(plans)
+    if n == 0 or len(u0s) != n:
+        raise ValueError("one u0 per plan")
+    hs = (_P * n)(*[p._h for p in plans])
+    u0p = (_P * n)(*[_ptr(u, "u0", p.nx) for p, u in zip(plans, u0s)])
+    tols = (_D * n)(*([float(tol)] * n if not hasattr(tol, "__len__") else tol))
+    mx = [int(maxit)] * n if not hasattr(maxit, "__len__") else [int(x) for x in maxit]
+    maxits = (_I * n)(*mx)
+    outs, outp = [], (_P * n)()
+    for i, p in enumerate(plans):
+        rows = {"none": 0, "final": 1, "cpoints": p.nc + 1, "all": p.nt + 1}[out]
+        t = None
+        if out != "none":
+            t = torch.empty((rows, p.nx), dtype=torch.float64, device=u0s[i].device)
+            outp[i] = t.data_ptr()
+        outs.append(t)
+    kinds = (_I * n)(*([OUT[out]] * n))
+    hists = [(_D * (mx[i] + 1))() for i in range(n)]
+    histp = (_P * n)(*[ctypes.cast(h, _P) for h in hists])
+    its = (_I * n)()
+    sts = (_I * n)()
+    rc = lib().mgrit_solve_batch(n, hs, u0p, None, tols, maxits,
+                                 outp if out != "none" else None, kinds, histp, its, sts)
+    _check(rc, "mgrit_solve_batch")
+    res = []
+    for i, p in enumerate(plans):
+        if sts[i] not in (OK, ENOTCONV, EDIVERGED):
+            raise MgritError(sts[i], "mgrit_solve_batch")
+        res.append(p._result(sts[i], its[i], hists[i], outs[i]))
+    return res
 
 
 class ServerStats(ctypes.Structure):
@@ -92,6 +130,10 @@ _SIGS = {
                                ctypes.POINTER(Taps), _I, _I, _I, _P]),
     "mgrit_solve": (_I, [_P, _P, _P, _D, _I, _P, _I, ctypes.POINTER(_D),
                          ctypes.POINTER(_I)]),
+    "mgrit_solve_batch": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                               ctypes.POINTER(_P), ctypes.POINTER(_D), ctypes.POINTER(_I),
+                               ctypes.POINTER(_P), ctypes.POINTER(_I), ctypes.POINTER(_P),
+                               ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "phi_apply_batch": (_I, [_P, _P, _P, _I, _I]),
     "mgrit_plan_bytes": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "mgrit_plan_set_seed": (_I, [_P, ctypes.c_ulonglong]),
@@ -282,12 +324,15 @@ class Plan:
                                OUT[out], hist, ctypes.byref(it))
         if rc not in (OK, ENOTCONV, EDIVERGED):
             raise MgritError(rc, "mgrit_solve")
+        return self._result(rc, it.value, hist, u_out)
+
+    def _result(self, rc, iters, hist, u_out):
         st = self.stats()
         # one norm per correction; FP32 Parareal (F-relaxation) records one
         # per FP64 refinement step instead
         refine = self.precision == "fp32" and self.relax == "F"
-        nh = (st.outer_iterations if refine else it.value) + 1
-        return SolveResult(rc, it.value, list(hist[:nh]), u_out, st)
+        nh = (st.outer_iterations if refine else iters) + 1
+        return SolveResult(rc, iters, list(hist[:nh]), u_out, st)
 
     def phi_apply_batch(self, inp, out, ksteps):
         b = inp.numel() // self.nx
