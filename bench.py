@@ -232,6 +232,7 @@ def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
             "setup_threads": setup_threads, "hbm_budget_gib": budget_gib,
             "hbm_peak_gib": round(st.hbm_peak / (1 << 30), 3),
             "psi_cache_hits": st.psi_cache_hits, "psi_cache_misses": st.psi_cache_misses,
+            "batches": st.batches, "batched_requests": st.batched_requests,
             "saturated": {"makespan_s": round(span, 3), "requests_per_s": round(rate, 2),
                           "dof_per_s": dof / span,
                           "p50_ms": round(float(np.percentile(lat_sat, 50)), 3),

@@ -14,10 +14,17 @@
  *               admitted in submission order, a later request may pass one
  *               that does not fit yet at most `max_bypass` times before
  *               admission waits for it (setup itself runs on several threads,
- *               so a request may become ready before an earlier one);
- *   run      -> on the slot's own HIP stream, so the kernels of all
- *               admitted requests overlap on the device; the solve state
- *               stays in device memory until the request completes;
+ *               so a request may become ready before an earlier one); the
+ *               admitted request takes the slot together with up to
+ *               max_batch-1 later ready requests of the same shape (n_x,
+ *               n_t, scheme, m, levels, cycle, relaxation, precision) that
+ *               fit, each of which passes the requests between it and the
+ *               first (counted against the same bypass limit);
+ *   run      -> the slot's group on the slot's own HIP stream as one
+ *               mgrit_solve_batch (relaxation launches of the group merged),
+ *               so the kernels of all admitted requests overlap on the
+ *               device; the solve state stays in device memory until the
+ *               group completes;
  *   complete -> the final time level is copied to the host, the plan and
  *               its memory are released and the next request can enter.
  * Conventions: return 0 or a negative MGRIT_E* code (mgrit.h); all
@@ -68,14 +75,16 @@ typedef struct {
     long long submitted, completed, active, waiting;
     size_t hbm_in_use, hbm_peak, hbm_budget;
     long long psi_cache_hits, psi_cache_misses;
+    long long batches;           /* groups of two or more requests run    */
+    long long batched_requests;  /* requests in those groups               */
 } mgrit_server_stats;
 
 /* Start a server: `hbm_budget` device bytes for resident plans, `slots`
- * requests running at once (each with its own HIP stream and host thread),
+ * groups running at once (each with its own HIP stream and host thread),
  * `setup_threads` host threads for the coarse-operator setup, `max_bypass`
- * (see above). */
+ * and `max_batch` (1..8; 1 runs every request alone) as above. */
 int mgrit_server_create(mgrit_server_t* server, size_t hbm_budget, int slots,
-                        int setup_threads, int max_bypass);
+                        int setup_threads, int max_bypass, int max_batch);
 
 /* Queue one request; *id receives its id.  Fails with MGRIT_EINVAL for an
  * invalid request and MGRIT_EBUSY if its footprint exceeds the whole budget. */

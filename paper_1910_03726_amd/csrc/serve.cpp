@@ -2,15 +2,18 @@
 //
 // Threads: `setup_threads` workers compute coarse operators on the host
 // (with a cache); `slots` workers each own a HIP stream and run one admitted
-// request at a time on it, so the kernels of all resident requests overlap
-// on the device.  Admission (under one mutex) happens whenever a request
-// becomes ready or a slot frees its memory.
+// group at a time on it -- a request and up to max_batch-1 later ones of the
+// same shape, solved together with merged relaxation launches -- so the
+// kernels of all resident requests overlap on the device.  Admission (under
+// one mutex) happens whenever a request becomes ready or a slot frees its
+// memory.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -50,18 +53,42 @@ struct Server {
   std::mutex mu;
   std::condition_variable cv;
   std::map<long long, std::shared_ptr<Req>> reqs;
-  std::deque<std::shared_ptr<Req>> setup_q, ready_q, run_q;
+  typedef std::vector<std::shared_ptr<Req>> Group;  // requests run as one batch
+  std::deque<std::shared_ptr<Req>> setup_q;
+  std::list<std::shared_ptr<Req>> ready_q;  // by submission order
+  std::deque<Group> run_q;
   std::map<PsiKey, std::vector<Taps>> psi_cache;
   long long next_id = 1, submitted = 0, completed = 0, admitted = 0, hits = 0, misses = 0;
   size_t budget = 0, in_use = 0, peak = 0;
-  int free_slots = 0, max_bypass = 0, device = 0;
+  int free_slots = 0, max_bypass = 0, max_batch = 1, device = 0;
+  long long batches = 0, batched = 0;  // groups of >= 2 requests, their requests
   bool stopping = false;
   std::vector<std::thread> workers;
+
+  // Requests whose relaxation launches can merge: the same plan shapes.
+  static bool same_shape(const Req& a, const Req& b) {
+    return a.r.nx == b.r.nx && a.r.nt == b.r.nt && a.r.scheme == b.r.scheme &&
+           a.r.m == b.r.m && a.levels == b.levels && a.r.cycle == b.r.cycle &&
+           a.r.relax == b.r.relax && a.r.precision == b.r.precision;
+  }
+
+  void admit(Req& q, Group& g, const std::shared_ptr<Req>& sp) {
+    in_use += q.bytes;
+    if (in_use > peak) peak = in_use;
+    q.state = Req::RUNNING;
+    q.t_admit = now_ms();
+    q.res.admit_seq = admitted++;
+    g.push_back(sp);
+  }
 
   // Admit ready requests in submission order while slots and budget allow.
   // A ready request that does not fit may be passed (a later one admitted
   // before it) at most max_bypass times; then admission waits for it.
-  // Requests still in setup do not hold others back.  Caller holds `mu`.
+  // Requests still in setup do not hold others back.  An admitted request
+  // takes a slot and brings along up to max_batch-1 later ready requests of
+  // the same shape that fit (solved with it as one batch); each of those
+  // passes the requests between, which counts against their bypass limit
+  // too.  Caller holds `mu`.
   void try_admit() {
     std::vector<Req*> blocked;
     for (auto it = ready_q.begin(); it != ready_q.end() && free_slots > 0;) {
@@ -69,14 +96,34 @@ struct Server {
       if (in_use + q.bytes <= budget) {
         bool stop = false;
         for (Req* bq : blocked) stop |= ++bq->bypassed >= max_bypass;
-        in_use += q.bytes;
-        if (in_use > peak) peak = in_use;
-        --free_slots;
-        q.state = Req::RUNNING;
-        q.t_admit = now_ms();
-        q.res.admit_seq = admitted++;
-        run_q.push_back(*it);
+        Group g;
+        admit(q, g, *it);
         it = ready_q.erase(it);
+        std::vector<Req*> passed;
+        for (auto jt = it; !stop && jt != ready_q.end() && (int)g.size() < max_batch;) {
+          Req& x = **jt;
+          if (!same_shape(q, x) || in_use + x.bytes > budget) {
+            passed.push_back(&x);
+            ++jt;
+            continue;
+          }
+          bool full = false;
+          for (Req* p : passed) full |= p->bypassed >= max_bypass;
+          for (Req* bq : blocked) full |= bq->bypassed >= max_bypass;
+          if (full) break;
+          for (Req* p : passed) ++p->bypassed;
+          for (Req* bq : blocked) ++bq->bypassed;
+          const bool at_it = jt == it;
+          admit(x, g, *jt);
+          jt = ready_q.erase(jt);
+          if (at_it) it = jt;
+        }
+        if (g.size() > 1) {
+          ++batches;
+          batched += (long long)g.size();
+        }
+        --free_slots;
+        run_q.push_back(std::move(g));
         cv.notify_all();
         if (stop) break;
         continue;
@@ -149,71 +196,106 @@ struct Server {
     // slot's setup never waits for the kernels of the others
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
     for (;;) {
-      std::shared_ptr<Req> q;
+      Group g;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return stopping || !run_q.empty(); });
         if (run_q.empty()) break;
-        q = run_q.front();
+        g = std::move(run_q.front());
         run_q.pop_front();
       }
-      run(*q, stream);
+      run(g, stream);
       std::lock_guard<std::mutex> lk(mu);
-      in_use -= q->bytes;
+      const double t = now_ms();
+      for (auto& q : g) {
+        in_use -= q->bytes;
+        q->state = Req::DONE;
+        q->t_done = t;
+        ++completed;
+      }
       ++free_slots;
-      q->state = Req::DONE;
-      q->t_done = now_ms();
-      ++completed;
       try_admit();
       cv.notify_all();
     }
     if (stream) (void)hipStreamDestroy(stream);
   }
 
-  void run(Req& q, hipStream_t stream) {
-    const mgrit_request& r = q.r;
-    std::vector<mgrit_taps> taps(q.psi.size());
-    for (size_t l = 0; l < q.psi.size(); ++l) {
-      taps[l].nnz = (int)q.psi[l].off.size();
-      taps[l].offset = q.psi[l].off.data();
-      taps[l].weight = q.psi[l].w.data();
-    }
-    mgrit_plan_t plan = nullptr;
-    int rc = mgrit_plan_create(&plan, r.nx, r.nt, r.alpha, r.cfl, r.scheme, r.m, q.levels,
-                               taps.data(), r.cycle, r.relax, r.precision, stream);
-    q.res.status = rc;
-    if (rc != MGRIT_OK) return;
-    double* dev = nullptr;
-    size_t row = (size_t)r.nx * sizeof(double);
-    if (mgr::dev_alloc((void**)&dev, 2 * row) != MGRIT_OK) {
-      q.res.status = MGRIT_ENOMEM;
-      mgrit_destroy(plan);
-      return;
-    }
-    size_t pb = 0;
-    mgrit_plan_bytes(plan, &pb);
-    q.res.hbm_bytes = pb + 2 * row;
-    if (hipMemcpyAsync(dev, q.u0.data(), row, hipMemcpyHostToDevice, stream) != hipSuccess) {
-      q.res.status = MGRIT_EHIP;
-    } else {
-      mgrit_plan_set_seed(plan, r.seed);
-      int it = 0;
-      rc = mgrit_solve(plan, dev, nullptr, r.tol, r.maxit, dev + r.nx, MGRIT_OUT_FINAL,
-                       nullptr, &it);
-      mgrit_stats st;
-      mgrit_get_stats(plan, &st);
+  // One group on the slot's stream: a plan per request, then all solves
+  // together (mgrit_solve_batch), the final time levels back to the host,
+  // and the plans released.
+  void run(Group& g, hipStream_t stream) {
+    struct Run {
+      Req* q;
+      mgrit_plan_t plan = nullptr;
+      double* dev = nullptr;  // u0 and the final time level
+    };
+    std::vector<Run> rs;
+    for (auto& sp : g) {
+      Req& q = *sp;
+      const mgrit_request& r = q.r;
+      std::vector<mgrit_taps> taps(q.psi.size());
+      for (size_t l = 0; l < q.psi.size(); ++l) {
+        taps[l].nnz = (int)q.psi[l].off.size();
+        taps[l].offset = q.psi[l].off.data();
+        taps[l].weight = q.psi[l].w.data();
+      }
+      Run x{&q};
+      int rc = mgrit_plan_create(&x.plan, r.nx, r.nt, r.alpha, r.cfl, r.scheme, r.m, q.levels,
+                                 taps.data(), r.cycle, r.relax, r.precision, stream);
+      const size_t row = (size_t)r.nx * sizeof(double);
+      if (rc == MGRIT_OK && mgr::dev_alloc((void**)&x.dev, 2 * row) != MGRIT_OK)
+        rc = MGRIT_ENOMEM;
+      if (rc == MGRIT_OK &&
+          hipMemcpyAsync(x.dev, q.u0.data(), row, hipMemcpyHostToDevice, stream) != hipSuccess)
+        rc = MGRIT_EHIP;
       q.res.status = rc;
-      q.res.iterations = it;
-      q.res.final_residual = st.final_residual;
-      q.ufinal.resize(r.nx);
-      if (hipMemcpyAsync(q.ufinal.data(), dev + r.nx, row, hipMemcpyDeviceToHost, stream) !=
-              hipSuccess ||
-          hipStreamSynchronize(stream) != hipSuccess)
-        q.res.status = MGRIT_EHIP;
+      if (rc != MGRIT_OK) {
+        mgr::dev_free(x.dev);
+        mgrit_destroy(x.plan);
+        continue;
+      }
+      size_t pb = 0;
+      mgrit_plan_bytes(x.plan, &pb);
+      q.res.hbm_bytes = pb + 2 * row;
+      mgrit_plan_set_seed(x.plan, r.seed);
+      rs.push_back(x);
     }
-    (void)hipStreamSynchronize(stream);
-    mgr::dev_free(dev);
-    mgrit_destroy(plan);
+    const int n = (int)rs.size();
+    if (n > 0) {
+      std::vector<mgrit_plan_t> plans(n);
+      std::vector<const double*> u0(n);
+      std::vector<double*> out(n);
+      std::vector<double> tol(n);
+      std::vector<int> maxit(n), kind(n, MGRIT_OUT_FINAL), iters(n, 0), status(n, MGRIT_OK);
+      for (int i = 0; i < n; ++i) {
+        plans[i] = rs[i].plan;
+        u0[i] = rs[i].dev;
+        out[i] = rs[i].dev + rs[i].q->r.nx;
+        tol[i] = rs[i].q->r.tol;
+        maxit[i] = rs[i].q->r.maxit;
+      }
+      const int rc = mgrit_solve_batch(n, plans.data(), u0.data(), nullptr, tol.data(),
+                                       maxit.data(), out.data(), kind.data(), nullptr,
+                                       iters.data(), status.data());
+      for (int i = 0; i < n; ++i) {
+        Req& q = *rs[i].q;
+        mgrit_stats st;
+        mgrit_get_stats(rs[i].plan, &st);
+        q.res.status = rc == MGRIT_EINVAL ? rc : status[i];
+        q.res.iterations = iters[i];
+        q.res.final_residual = st.final_residual;
+        q.ufinal.resize(q.r.nx);
+        if (hipMemcpyAsync(q.ufinal.data(), out[i], (size_t)q.r.nx * sizeof(double),
+                           hipMemcpyDeviceToHost, stream) != hipSuccess)
+          q.res.status = MGRIT_EHIP;
+      }
+      if (hipStreamSynchronize(stream) != hipSuccess)
+        for (auto& x : rs) x.q->res.status = MGRIT_EHIP;
+    }
+    for (auto& x : rs) {
+      mgr::dev_free(x.dev);
+      mgrit_destroy(x.plan);
+    }
   }
 };
 
@@ -234,8 +316,9 @@ using namespace mgr;
 extern "C" {
 
 int mgrit_server_create(mgrit_server_t* out, size_t budget, int slots, int setup_threads,
-                        int max_bypass) {
-  if (!out || slots < 1 || setup_threads < 1 || max_bypass < 0 || budget == 0)
+                        int max_bypass, int max_batch) {
+  if (!out || slots < 1 || setup_threads < 1 || max_bypass < 0 || budget == 0 ||
+      max_batch < 1 || max_batch > kMaxBatch)
     return MGRIT_EINVAL;
   *out = nullptr;
   Server* S = new (std::nothrow) Server();
@@ -243,6 +326,7 @@ int mgrit_server_create(mgrit_server_t* out, size_t budget, int slots, int setup
   S->budget = budget;
   S->free_slots = slots;
   S->max_bypass = max_bypass;
+  S->max_batch = max_batch;
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
     return MGRIT_ENODEV;
@@ -340,6 +424,8 @@ int mgrit_server_get_stats(mgrit_server_t server, mgrit_server_stats* st) {
   st->hbm_budget = S->budget;
   st->psi_cache_hits = S->hits;
   st->psi_cache_misses = S->misses;
+  st->batches = S->batches;
+  st->batched_requests = S->batched;
   return MGRIT_OK;
 }
 

@@ -112,7 +112,8 @@ class ServerStats(ctypes.Structure):
                 ("active", ctypes.c_longlong), ("waiting", ctypes.c_longlong),
                 ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
                 ("hbm_budget", ctypes.c_size_t), ("psi_cache_hits", ctypes.c_longlong),
-                ("psi_cache_misses", ctypes.c_longlong)]
+                ("psi_cache_misses", ctypes.c_longlong), ("batches", ctypes.c_longlong),
+                ("batched_requests", ctypes.c_longlong)]
 
 
 _P = ctypes.c_void_p
@@ -145,7 +146,7 @@ _SIGS = {
     "mgrit_destroy": (None, [_P]),
     "mgrit_plan_estimate_bytes": (_I, [_I, _I, _I, _I, _I,
                                        ctypes.POINTER(ctypes.c_size_t)]),
-    "mgrit_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _I, _I]),
+    "mgrit_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _I, _I, _I]),
     "mgrit_server_submit": (_I, [_P, ctypes.POINTER(Request),
                                  ctypes.POINTER(ctypes.c_longlong)]),
     "mgrit_server_wait": (_I, [_P, ctypes.c_longlong, _I, ctypes.POINTER(Result),
@@ -385,10 +386,11 @@ def estimate_bytes(nx, nt, m, levels, precision="fp64"):
 class Server:
     """Continuous-batching server (include/mgrit_serve.h)."""
 
-    def __init__(self, hbm_budget, slots=8, setup_threads=8, max_bypass=4):
+    def __init__(self, hbm_budget, slots=8, setup_threads=8, max_bypass=4, max_batch=8):
         h = _P()
         _check(lib().mgrit_server_create(ctypes.byref(h), int(hbm_budget), slots,
-                                         setup_threads, max_bypass), "mgrit_server_create")
+                                         setup_threads, max_bypass, max_batch),
+               "mgrit_server_create")
         self._h = h
 
     def submit(self, nx, nt, scheme, cfl, m, u0, levels=0, cycle="V", relax="FCF",

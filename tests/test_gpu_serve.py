@@ -57,6 +57,34 @@ def test_results_identical_alone_and_in_the_mix():
         assert np.array_equal(ua, ub)
 
 
+def test_same_shape_requests_run_as_batches():
+    # two shapes, Courant numbers and initial values all different; with one
+    # slot the queue builds up and requests of a shape are solved together
+    base = _mix(1, seed=5)[0]
+    reqs = []
+    for k in range(16):
+        q = dict(base, nx=512, nt=2048, m=4, scheme="ERK3" if k % 2 else "ERK1",
+                 precision="fp64", init_seed=50 + k, u0_seed=900 + k)
+        q["cfl"] = rk.paper_cfl(q["scheme"], 0.5 + 0.025 * k)
+        reqs.append(q)
+    alone = []
+    with M.Server(64 * GiB, slots=1, setup_threads=2, max_batch=1) as S:
+        for q in reqs:
+            res, u = S.wait(_submit(S, q), q["nx"])
+            assert res.status == M.OK
+            alone.append((res.iterations, u))
+        assert S.stats().batches == 0
+    with M.Server(64 * GiB, slots=1, setup_threads=4, max_batch=4) as S:
+        ids = [_submit(S, q) for q in reqs]
+        got = [S.wait(i, q["nx"]) for i, q in zip(ids, reqs)]
+        st = S.stats()
+    assert st.batches >= 1 and st.batched_requests >= 2
+    for (ia, ua), (res, ub) in zip(alone, got):
+        assert res.status == M.OK
+        assert ia == res.iterations
+        assert np.array_equal(ua, ub)
+
+
 def test_results_match_the_oracle():
     reqs = _mix(6, seed=12)
     with M.Server(64 * GiB, slots=3, setup_threads=3) as S:
@@ -82,7 +110,7 @@ def test_admission_respects_budget_and_bypass_limit():
     b_big = M.estimate_bytes(2048, 8192, 4, L_big) + 2 * 2048 * 8
     budget = b_big + b_small // 2
     assert 4 * b_small <= budget
-    with M.Server(budget, slots=4, setup_threads=1, max_bypass=2) as S:
+    with M.Server(budget, slots=4, setup_threads=1, max_bypass=2, max_batch=1) as S:
         for q in (small[0], big):
             res, _ = S.wait(_submit(S, q), q["nx"])
             assert res.status == M.OK
