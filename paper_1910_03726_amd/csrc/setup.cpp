@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <memory>
+#include <mutex>
 
 #include "../../include/mgrit.h"
 
@@ -230,18 +232,31 @@ bool erk_taps(const Tableau& t, double cfl, int nx, Taps& out) {
 // DFTs with exactly reduced angles
 // ---------------------------------------------------------------------------
 static void roots_of_unity(int n, std::vector<cd>& w) {
-  // w[q] = exp(-2 pi i q / n)
-  w.resize(n);
-  for (int q = 0; q < n; ++q) {
-    double a = -2.0 * kPi * (double)q / (double)n;
-    w[q] = cd(std::cos(a), std::sin(a));
+  // w[q] = exp(-2 pi i q / n); tables are kept per n (setup threads share them)
+  static std::mutex mu;
+  static std::map<int, std::shared_ptr<const std::vector<cd>>> cache;
+  std::shared_ptr<const std::vector<cd>> tab;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(n);
+    if (it != cache.end()) tab = it->second;
   }
+  if (!tab) {
+    auto v = std::make_shared<std::vector<cd>>(n);
+    for (int q = 0; q < n; ++q) {
+      double a = -2.0 * kPi * (double)q / (double)n;
+      (*v)[q] = cd(std::cos(a), std::sin(a));
+    }
+    tab = v;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() < 64) cache.emplace(n, tab);
+  }
+  w = *tab;
 }
 
-void dft(std::vector<cd>& a, bool inverse) {
+// The transform with the roots of unity w (roots_of_unity of a.size()).
+static void dft_with(std::vector<cd>& a, bool inverse, const std::vector<cd>& w) {
   const int n = (int)a.size();
-  std::vector<cd> w;
-  roots_of_unity(n, w);
   if (n > 0 && (n & (n - 1)) == 0) {
     // iterative radix-2
     for (int i = 1, j = 0; i < n; ++i) {
@@ -251,15 +266,15 @@ void dft(std::vector<cd>& a, bool inverse) {
       if (i < j) std::swap(a[i], a[j]);
     }
     for (int len = 2; len <= n; len <<= 1) {
-      const int step = n / len;
-      for (int i = 0; i < n; i += len)
-        for (int k = 0; k < len / 2; ++k) {
-          cd tw = w[k * step];
-          if (inverse) tw = std::conj(tw);
-          cd u = a[i + k], v = a[i + k + len / 2] * tw;
-          a[i + k] = u + v;
-          a[i + k + len / 2] = u - v;
+      const int step = n / len, half = len / 2;
+      for (int k = 0; k < half; ++k) {
+        const cd tw = inverse ? std::conj(w[k * step]) : w[k * step];
+        for (int i = k; i < n; i += len) {
+          const cd u = a[i], v = a[i + half] * tw;
+          a[i] = u + v;
+          a[i + half] = u - v;
         }
+      }
     }
   } else {
     std::vector<cd> out(n);
@@ -277,10 +292,22 @@ void dft(std::vector<cd>& a, bool inverse) {
     for (auto& x : a) x /= (double)n;
 }
 
+void dft(std::vector<cd>& a, bool inverse) {
+  std::vector<cd> w;
+  roots_of_unity((int)a.size(), w);
+  dft_with(a, inverse, w);
+}
+
 void taps_eigs(const Taps& t, int nx, std::vector<cd>& mu) {
   std::vector<cd> w;
   roots_of_unity(nx, w);
   mu.assign(nx, cd(0.0));
+  if (nx > 0 && (nx & (nx - 1)) == 0) {
+    // mu = forward transform of the taps placed at their offsets
+    for (size_t q = 0; q < t.off.size(); ++q) mu[((t.off[q] % nx) + nx) % nx] += t.w[q];
+    dft_with(mu, false, w);
+    return;
+  }
   for (size_t q = 0; q < t.off.size(); ++q) {
     long long o = ((t.off[q] % nx) + nx) % nx;
     for (int k = 0; k < nx; ++k) mu[k] += t.w[q] * w[(int)((k * o) % nx)];
@@ -298,10 +325,102 @@ static cd ipow(cd z, int m) {
 }
 
 // ---------------------------------------------------------------------------
-// Eq. (9): complex Householder QR least squares
+// Eq. (9) by its normal equations, refined against the full spectrum
+// ---------------------------------------------------------------------------
+// With e_t(k) = e^{-2 pi i k o_t / n} the columns and w_k the weights, the
+// normal matrix G[t][s] = Re sum_k w_k conj(e_t(k)) e_s(k) depends only on
+// o_t - o_s: it is the real part of c(d) = sum_k w_k e^{2 pi i k d / n}, one
+// inverse FFT of the weights.  Likewise A^T W r for any spectral residual r
+// is an inverse FFT read at the offsets, and the model sum_t x_t e_t(k) one
+// forward FFT of the sparse tap vector.  The Cholesky solution of G loses
+// digits to cond(G) (up to ~1e15 on deep levels), so it is refined: each
+// step recomputes the residual from the spectrum and solves G again, which
+// contracts the error by about cond(G) * eps per step.  O(n log n + v^3)
+// per level instead of O(n v^2).  False if n is not a power of two or the
+// refinement does not settle (the caller then uses the QR solution).
+static bool lsq_psi_spectral(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
+                             std::vector<double>& x) {
+  const int n = (int)lam.size();
+  const int v = (int)offs.size();
+  if (n < 2 || (n & (n - 1)) != 0 || v < 1 || v > n) return false;
+  std::vector<int> o(v);
+  for (int t = 0; t < v; ++t) o[t] = ((offs[t] % n) + n) % n;
+  std::vector<double> wk(n);
+  std::vector<cd> target(n), c(n), h(n);
+  for (int k = 0; k < n; ++k) {
+    const double sw = 1.0 / (1.0 - std::abs(lam[k]) + 1e-6);
+    wk[k] = sw * sw;
+    target[k] = ipow(lam[k], m);
+    c[k] = wk[k];
+    h[k] = wk[k] * target[k];
+  }
+  std::vector<cd> ru;
+  roots_of_unity(n, ru);
+  dft_with(c, true, ru);  // c[d] * n = sum_k w_k e^{+2 pi i k d / n}
+  dft_with(h, true, ru);
+  std::vector<double> G((size_t)v * v), L((size_t)v * v, 0.0), g(v);
+  for (int t = 0; t < v; ++t) {
+    for (int q = 0; q < v; ++q) G[(size_t)t * v + q] = n * c[((o[t] - o[q]) % n + n) % n].real();
+    g[t] = n * h[o[t]].real();
+  }
+  // Cholesky G = L L^T
+  for (int j = 0; j < v; ++j) {
+    double d = G[(size_t)j * v + j];
+    for (int q = 0; q < j; ++q) d -= L[(size_t)j * v + q] * L[(size_t)j * v + q];
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * v + j] = ljj;
+    for (int i = j + 1; i < v; ++i) {
+      double s = G[(size_t)i * v + j];
+      for (int q = 0; q < j; ++q) s -= L[(size_t)i * v + q] * L[(size_t)j * v + q];
+      L[(size_t)i * v + j] = s / ljj;
+    }
+  }
+  auto solve = [&](std::vector<double>& b) {
+    for (int i = 0; i < v; ++i) {
+      double s = b[i];
+      for (int q = 0; q < i; ++q) s -= L[(size_t)i * v + q] * b[q];
+      b[i] = s / L[(size_t)i * v + i];
+    }
+    for (int i = v - 1; i >= 0; --i) {
+      double s = b[i];
+      for (int q = i + 1; q < v; ++q) s -= L[(size_t)q * v + i] * b[q];
+      b[i] = s / L[(size_t)i * v + i];
+    }
+  };
+  x = g;
+  solve(x);
+  double prev = 1e300;
+  std::vector<cd> r(n);
+  for (int it = 0; it < 40; ++it) {
+    // spectral residual r_k = target_k - sum_t x_t e_t(k), weighted, back
+    std::fill(r.begin(), r.end(), cd(0.0));
+    for (int t = 0; t < v; ++t) r[o[t]] += x[t];
+    dft_with(r, false, ru);
+    for (int k = 0; k < n; ++k) r[k] = wk[k] * (target[k] - r[k]);
+    dft_with(r, true, ru);
+    std::vector<double> dx(v);
+    for (int t = 0; t < v; ++t) dx[t] = n * r[o[t]].real();
+    solve(dx);
+    double nd = 0.0, nx = 0.0;
+    for (int t = 0; t < v; ++t) {
+      x[t] += dx[t];
+      nd = std::max(nd, std::fabs(dx[t]));
+      nx = std::max(nx, std::fabs(x[t]));
+    }
+    if (nd <= 1e-13 * nx) return true;
+    if (it >= 2 && nd > 0.5 * prev) return nd <= 1e-12 * nx;  // at its rounding floor
+    prev = nd;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (9): Householder QR least squares (fallback)
 // ---------------------------------------------------------------------------
 double lsq_psi(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
                std::vector<double>& wout) {
+  if (lsq_psi_spectral(lam, m, offs, wout)) return 0.0;  // real by construction
   // Rows k of eq. (9): sqrt(w_k) [e^{-2 pi i k o_t / n}]_t against
   // sqrt(w_k) lambda_k^m.  The symbols of a real stencil satisfy
   // lambda_{n-k} = conj(lambda_k), so rows k and n-k are conjugate and, for
@@ -465,7 +584,17 @@ int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
   }
   if (rule != MGRIT_PSI_WINDOW && rule != MGRIT_PSI_ETA) return MGRIT_EINVAL;
   std::vector<cd> lam(nx);
-  for (int k = 0; k < nx; ++k) lam[k] = step_symbol(t, cfl, 2.0 * kPi * k / nx);
+  {
+    std::vector<int> off;
+    std::vector<double> d;
+    upwind(t.p, off, d);
+    for (int k = 0; k < nx; ++k) {
+      const double th = 2.0 * kPi * k / nx;
+      cd z = 0.0;
+      for (size_t j = 0; j < off.size(); ++j) z += d[j] * std::exp(cd(0.0, off[j] * th));
+      lam[k] = stability(t, -cfl * z);  // step_symbol at th
+    }
+  }
   int nnz_prev = 0;
   if (!t.implicit) {
     Taps f;
