@@ -151,10 +151,14 @@ int mgrit_phi_taps(int scheme, double cfl, int nx, int capacity, int* offsets,
  *   MGRIT_PSI_REDISC: ERK only; Psi_l = the ERK stencil at Courant number
  *       m^(l-1) c (no least squares).
  * Weights w_k = 1/(1 - |lambda_k| + 1e-6)^2 on the eigenvalues of Phi_l.
- * Eq. (9) is solved in its real form: for a real stepper the rows k and
+ * Eq. (9) is solved for real weights: for a real stepper the rows k and
  * n_x - k are complex conjugates, so the minimiser over complex weights is
- * real and equals the least-squares solution over k <= n_x/2 with real and
- * imaginary parts as separate equations (Householder QR).
+ * real.  For n_x a power of two through its normal equations (the Gram
+ * matrix of the weighted Fourier columns depends only on offset
+ * differences: one FFT of the weights), refined against the residual over
+ * the whole spectrum until the correction is below 1e-13 of the weights;
+ * otherwise, or if the refinement stalls, by Householder QR of the real
+ * form (k <= n_x/2, real and imaginary parts as separate equations).
  * out[l-2] for l = 2..levels must carry arrays with room for out[.].nnz
  * taps (capacity on input, count on output).  *max_imag (may be NULL)
  * receives the largest imaginary part of the weights, 0 in the real form
