@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -56,7 +58,10 @@ def _inputs(w, torch):
     return u0, uinit
 
 
-def _timed_solves(P, u0, uinit, steps, warmup, torch):
+def _timed_solves(P, u0, uinit, steps, warmup, torch, each=None):
+    """Mean seconds per solve over `steps` timed solves (after `warmup`);
+    each solve returns only once its GPU work is done, so `each` (a list)
+    receives the per-solve times too."""
     out = torch.empty((1, P.nx), dtype=torch.float64, device="cuda")
     res = None
     for _ in range(warmup):
@@ -64,7 +69,10 @@ def _timed_solves(P, u0, uinit, steps, warmup, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
+        t1 = time.perf_counter()
         res = P.solve(u0, uinit, tol=TOL, maxit=100, out="final", u_out=out)
+        if each is not None:
+            each.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
     return dt, res
@@ -129,6 +137,7 @@ def roofline(P, w, u0, uinit, torch, workload):
            "fp64_tflops_achieved": (round(flops_total / (ms * 1e-3) / 1e12, 2)
                                     if flops_total else None),
            "fp64_tflops_peak": FP64_PEAK_TFS,
+           "relaxation_dof_steps_per_s": prof["fine_dof_steps"] / (ms * 1e-3),
            "ms_by_class": {k: round(v, 4) for k, v in prof["ms"].items()},
            "launches_by_class": prof["launches"]}
     if out["bound"] == "alu":
@@ -272,6 +281,22 @@ def workload_line(name, steps, warmup, torch, precision=None):
     oc = P.operator_complexity()
     if oc == oc:
         d["operator_complexity"] = round(oc, 4)
+    # fine relaxation passes of one profiled solve (HIP events per launch):
+    # ERK passes do 2 nnz(Phi) flops per fine DOF-step; FP32 passes run at
+    # the FP64 vector rate (packed FP32 is not used), so both are priced
+    # against the FP64 vector peak
+    P.set_profiling(True)
+    P.solve(u0, uinit, tol=TOL, maxit=100, out="none")
+    prof = P.profile()
+    P.set_profiling(False)
+    nnz = _fine_nnz(w)
+    ms, n = prof["ms"]["relax_fine"], prof["launches"]["relax_fine"]
+    fp = {"launches": n, "avg_ms": round(ms / max(n, 1), 4)}
+    if nnz and ms > 0:
+        tf = 2.0 * nnz * prof["fine_dof_steps"] / (ms * 1e-3) / 1e12
+        fp.update({"tflops": round(tf, 2), "frac_of_fp64_vector_peak": round(tf / FP64_PEAK_TFS, 4)})
+    d["fine_pass"] = fp
+    d["ms_by_class"] = {k: round(v, 4) for k, v in prof["ms"].items()}
     P.close()
     return d
 
@@ -309,7 +334,8 @@ def main():
         del src, dst
     P, psi = _plan(w)
     u0, uinit = _inputs(w, torch)
-    dt, r = _timed_solves(P, u0, uinit, a.steps, a.warmup, torch)
+    each = []
+    dt, r = _timed_solves(P, u0, uinit, a.steps, a.warmup, torch, each)
     line = {"metric": METRIC, "value": w["nx"] * w["nt"] / dt, "unit": "DOF/s",
             "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
             "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
@@ -321,6 +347,9 @@ def main():
                        "levels": w["levels"], "cycle": w["cycle"], "tol": TOL,
                        "psi_nnz": [len(o) for o, _ in psi]},
             "iterations": r.iters, "final_residual": r.hist[-1],
+            "step_ms": {"median": round(1e3 * float(np.median(each)), 4),
+                        "p95": round(1e3 * float(np.percentile(each, 95)), 4),
+                        "min": round(1e3 * min(each), 4)},
             "kernels": P.describe()}
     line["roofline"] = roofline(P, w, u0, uinit, torch, a.workload)
     tseq = gpu_sequential(P, w, u0, torch)
