@@ -79,6 +79,11 @@ extern "C" {
 #define MGRIT_PSI_ETA 2      /* thresholding |phi^m| >= eta max (Sec. 4.6)    */
 #define MGRIT_PSI_REDISC 3   /* rediscretization: ERK Phi with step m^(l-1) dt */
 
+/* how the coarsest level's system is solved (mgrit_plan_set_coarse_solver) */
+#define MGRIT_COARSE_AUTO 0     /* the faster of the two by the plan's model   */
+#define MGRIT_COARSE_SWEEP 1    /* time step after time step, as written       */
+#define MGRIT_COARSE_SPECTRAL 2 /* per Fourier mode of the circulant Psi       */
+
 /* what mgrit_solve writes to u_out_dev */
 #define MGRIT_OUT_NONE 0     /* nothing                                       */
 #define MGRIT_OUT_FINAL 1    /* u^{n_t}: n_x values                           */
@@ -221,6 +226,25 @@ int mgrit_solve_batch(int n, const mgrit_plan_t* plans,
                       const int* maxit, double* const* u_out_dev,
                       const int* out_kind, double* const* res_hist_host,
                       int* iters_out, int* status);
+
+/* How solves on this plan compute the coarsest level's solution
+ * x^0 = 0, x^s = Psi x^(s-1) + g^s, s = 1..n (the exact coarse solve of
+ * Sec. 2.2 and 4.4):
+ *   MGRIT_COARSE_SWEEP:    the n steps one after another (launches of a
+ *                          few steps each, spatially tiled);
+ *   MGRIT_COARSE_SPECTRAL: Psi is circulant, so the discrete Fourier
+ *                          transform diagonalises it (Sec. 4.1): every row
+ *                          g^s is transformed, each Fourier mode k runs its
+ *                          own recurrence X^s_k = mu_k X^(s-1)_k + G^s_k
+ *                          (mu_k the eigenvalues of Psi), and the rows are
+ *                          transformed back -- the same solution up to
+ *                          rounding, in three launches instead of n steps;
+ *                          needs n_x a power of two up to 8192 (else
+ *                          MGRIT_EINVAL);
+ *   MGRIT_COARSE_AUTO:     (the default) the one the plan's cost model
+ *                          expects to be faster.
+ * mgrit_plan_describe reports "(spectral solve)" when it is used. */
+int mgrit_plan_set_coarse_solver(mgrit_plan_t plan, int mode);
 
 /* out[b] = Phi^k in[b] for b = 0..batch-1, rows of n_x values (device,
  * row-major, in and out may not overlap).  The fine stepper of the plan in

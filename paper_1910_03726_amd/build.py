@@ -35,6 +35,7 @@ def _jobs():
     objs.append((HIPCC, os.path.join(CSRC, "serve.cpp"), "serve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "solve.cpp"), "solve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
+    objs.append((HIPCC, os.path.join(CSRC, "spectral.hip"), "spectral.o", []))
     for prec in (0, 1):
         objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),
                      f"inst_sdirk_{prec}.o", [f"-DMGR_PREC={prec}"]))

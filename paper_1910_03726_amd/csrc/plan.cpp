@@ -258,6 +258,7 @@ int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, i
           tiled[1] = sh;
         }
       }
+      seq_us = best < 1e299 ? best : whole[1].est_us;
     }
   } else if (ok) {
     for (int io = 0; io < 2 && ok; ++io) {
@@ -369,6 +370,9 @@ void OpDesc::release() {
   dev_free(d_taps);
   dev_free(d_off);
   dev_free(d_sdirk);
+  dev_free(d_mu);
+  dev_free(d_tw);
+  d_mu = d_tw = nullptr;
   staged.clear();
   d_taps = nullptr;
   d_off = nullptr;
@@ -654,7 +658,33 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
     if (l < levels - 1) b += 2 * (size_t)(n / m + 1) * row;     // V_l, R_l
   }
   b += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);  // partials, norm
+  if (spectral_supported(nx))  // spectral coarsest solve: rows, eigenvalues, twiddles
+    b += spectral_rows((int)n) * nx * 16 + (size_t)nx * 16 + (size_t)(nx / 2) * 16;
   return b;
+}
+
+// Modelled time of one spectral coarsest-level solve of n steps (row
+// transforms, mode recurrences, inverse transforms), fitted to MI355X
+// traces: launch costs, about 3.5 us per four-stage pass of a transform, a
+// dependent load round trip of about 1.2 us per 16 steps of the
+// recurrences, 80 bytes of HBM traffic per point and step.
+static double spectral_time_us(int nx, int n) {
+  int lg = 0;
+  while ((1 << lg) < nx) ++lg;
+  const int passes = (lg + 3) / 4;
+  return 3 * 3.0 + 2 * (4.0 + 3.5 * passes) + 2.0 + ((n + 15) / 16) * 1.2 +
+         (double)(n + 1) * nx * 80.0 / 3.0e6;
+}
+
+int Plan::set_coarse_mode(int mode) {
+  if (mode != MGRIT_COARSE_AUTO && mode != MGRIT_COARSE_SWEEP && mode != MGRIT_COARSE_SPECTRAL)
+    return MGRIT_EINVAL;
+  if (mode == MGRIT_COARSE_SPECTRAL && !Sspec) return MGRIT_EINVAL;
+  coarse_mode = mode;
+  spectral = Sspec && (mode == MGRIT_COARSE_SPECTRAL ||
+                       (mode == MGRIT_COARSE_AUTO && spectral_us < lev.back().seq.seq_us));
+  description = description_levels + (spectral ? " (spectral solve)" : "");
+  return MGRIT_OK;
 }
 }  // namespace mgr
 
@@ -952,6 +982,26 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
         !(P->h_norm = take_host_word()))
       return fail(MGRIT_ENOMEM);
     P->bytes += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);
+    if (spectral_supported(nx)) {
+      // the coarsest stencil's eigenvalues and the transform's twiddles
+      Level& C = P->lev.back();
+      Taps f;
+      f.off.assign(psi[levels - 2].offset, psi[levels - 2].offset + psi[levels - 2].nnz);
+      f.w.assign(psi[levels - 2].weight, psi[levels - 2].weight + psi[levels - 2].nnz);
+      std::vector<cd> mu, tw(nx / 2);
+      taps_eigs(f, nx, mu);
+      for (int q = 0; q < nx / 2; ++q) {
+        const double a = -6.283185307179586476925286766559 * (double)q / (double)nx;
+        tw[q] = cd(std::cos(a), std::sin(a));
+      }
+      const size_t before = C.seq.bytes;
+      if (C.seq.upload((void**)&C.seq.d_mu, mu.data(), mu.size() * sizeof(cd)) ||
+          C.seq.upload((void**)&C.seq.d_tw, tw.data(), tw.size() * sizeof(cd)) ||
+          dev_alloc((void**)&P->Sspec, spectral_rows(C.n) * nx * sizeof(cd)) != MGRIT_OK)
+        return fail(MGRIT_ENOMEM);
+      P->bytes += C.seq.bytes - before + spectral_rows(C.n) * nx * sizeof(cd);
+      P->spectral_us = spectral_time_us(nx, C.n);
+    }
     std::string d;
     for (int l = 0; l < levels; ++l) {
       const OpDesc& o = (l == levels - 1) ? P->lev[l].seq : P->lev[l].op;
@@ -959,7 +1009,8 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
       snprintf(hdr, sizeof hdr, "L%d n=%d: ", l + 1, P->lev[l].n);
       d += hdr + o.describe() + (l + 1 < levels ? "; " : "");
     }
-    P->description = d;
+    P->description_levels = d;
+    (void)P->set_coarse_mode(MGRIT_COARSE_AUTO);
   } catch (...) {
     return fail(MGRIT_ENOMEM);
   }
@@ -985,7 +1036,7 @@ void mgrit_destroy(mgrit_plan_t plan) {
     dev_free(L.V);
     dev_free(L.R);
   }
-  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm}) dev_free(p);
+  for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm, P->Sspec}) dev_free(p);
   give_host_word(P->h_norm);
   for (auto& p : P->pending) {
     (void)hipEventDestroy(p.e0);
@@ -1013,6 +1064,11 @@ int mgrit_plan_set_seed(mgrit_plan_t plan, unsigned long long seed) {
   if (!plan) return MGRIT_EINVAL;
   reinterpret_cast<Plan*>(plan)->seed = seed;
   return MGRIT_OK;
+}
+
+int mgrit_plan_set_coarse_solver(mgrit_plan_t plan, int mode) {
+  if (!plan) return MGRIT_EINVAL;
+  return reinterpret_cast<Plan*>(plan)->set_coarse_mode(mode);
 }
 
 int mgrit_get_stats(mgrit_plan_t plan, mgrit_stats* s) {

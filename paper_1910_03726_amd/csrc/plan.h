@@ -46,6 +46,9 @@ struct OpDesc {
   size_t shmem[2] = {0, 0};             // dynamic LDS bytes per precision
   StencilShape whole[2], tiled[2];      // stencil: [no per-step IO, per-step IO]
   int seq_chunk = 0;                    // sequential sweeps: steps per launch
+  double seq_us = 1e300;                // sequential sweeps: modelled time of one
+  double* d_mu = nullptr;               // spectral solve: eigenvalues of the
+  double* d_tw = nullptr;               // operator and twiddles (complex)
   int NL = 0, K = 0;                    // lanes per workgroup, points per lane
   int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
   int ntaps = 0, nnz = 0;
@@ -119,7 +122,14 @@ struct Plan {
   double *partial = nullptr, *d_norm = nullptr, *h_norm = nullptr;
   unsigned long long seed = 1;
   size_t bytes = 0;
-  std::string description;
+  std::string description, description_levels;
+  // coarsest level: spectral solve (possible if S is allocated, chosen if
+  // `spectral`) or chunked sweeps
+  int coarse_mode = MGRIT_COARSE_AUTO;
+  bool spectral = false;
+  double* Sspec = nullptr;
+  double spectral_us = 0.0;
+  int set_coarse_mode(int mode);
   mgrit_stats stats = {};
   // profiling
   bool profiling = false;

@@ -48,4 +48,16 @@ void launch_axpy(double* y, const double* x, long long n, void* stream);
 void launch_uniform_init(double* out, long long rows, int nx, unsigned long long seed,
                          void* stream);
 
+// Spectral coarsest-level solve (spectral.hip): X rows 0..n of x^0 = 0,
+// x^s = Psi x^s-1 + g^s for g rows 1..n, with S room for spectral_rows(n)
+// x n_x complex values, mu the n_x eigenvalues of Psi and tw the twiddles
+// e^{-2 pi i q/n_x}, q < n_x/2 (complex = two doubles).  n_x a power of two
+// from 4 up to kSpectralMaxNx.  Returns 0, or -1 if the shape is not
+// supported or a launch failed.
+constexpr int kSpectralMaxNx = 8192;
+bool spectral_supported(int nx);
+size_t spectral_rows(int n);
+int launch_spectral_solve(const double* g, double* X, void* S, const void* mu, const void* tw,
+                          int nx, int n, void* stream);
+
 }  // namespace mgr

@@ -120,6 +120,23 @@ void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec);
 void coarse_solve(Group& G, const List& l0, int l, int kind, int prec) {
   List seq, rest;
   for (Member* M : live(l0)) (l == (int)M->P->lev.size() - 1 ? seq : rest).push_back(M);
+  // spectral solves first (direct launches), then the chunked sweeps
+  List sweep;
+  for (Member* M : seq) {
+    Plan* P = M->P;
+    if (!P->spectral) {
+      sweep.push_back(M);
+      continue;
+    }
+    Level& L = P->lev.back();
+    hipEvent_t e0 = nullptr;
+    P->mark_util(MGRIT_PROF_COARSEST, e0);
+    Group::check(M, launch_spectral_solve(rhs_of(M, l), L.X, P->Sspec, L.seq.d_mu,
+                                          L.seq.d_tw, P->nx, L.n, G.stream()) == 0
+                        ? MGRIT_OK : MGRIT_EHIP);
+    P->end_util(MGRIT_PROF_COARSEST, e0);
+  }
+  seq.swap(sweep);
   if (!seq.empty()) {
     // chunked sequential sweep: one launch per member per round
     std::vector<int> s0(seq.size(), 0);

@@ -26,6 +26,7 @@ OUT = {"none": 0, "final": 1, "cpoints": 2, "all": 3}
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EHIP, ENOTCONV, EDIVERGED, EIMAG, ENODEV, \
     ECAPACITY, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
+COARSE = {"auto": 0, "sweep": 1, "spectral": 2}
 PROF_CLASSES = ("relax_fine", "relax_coarse", "coarsest", "norm", "other")
 
 
@@ -138,6 +139,7 @@ _SIGS = {
     "phi_apply_batch": (_I, [_P, _P, _P, _I, _I]),
     "mgrit_plan_bytes": (_I, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "mgrit_plan_set_seed": (_I, [_P, ctypes.c_ulonglong]),
+    "mgrit_plan_set_coarse_solver": (_I, [_P, _I]),
     "mgrit_get_stats": (_I, [_P, ctypes.POINTER(Stats)]),
     "mgrit_set_profiling": (_I, [_P, _I]),
     "mgrit_get_profile": (_I, [_P, ctypes.POINTER(Profile)]),
@@ -264,7 +266,7 @@ class Plan:
     """An MGRIT plan on the current HIP device (see mgrit_plan_create)."""
 
     def __init__(self, nx, nt, cfl, scheme, m, levels, psi, alpha=1.0, cycle="V",
-                 relax="FCF", precision="fp64", stream=None):
+                 relax="FCF", precision="fp64", stream=None, coarse="auto"):
         import torch
         self.nx, self.nt, self.m, self.levels = int(nx), int(nt), int(m), int(levels)
         self.scheme = scheme
@@ -289,6 +291,13 @@ class Plan:
                                      ctypes.c_void_p(stream))
         _check(rc, "mgrit_plan_create")
         self._h = h
+        if coarse != "auto":
+            self.set_coarse_solver(coarse)
+
+    def set_coarse_solver(self, mode):
+        """'auto', 'sweep' or 'spectral' (mgrit_plan_set_coarse_solver)."""
+        _check(lib().mgrit_plan_set_coarse_solver(self._h, COARSE[mode]),
+               "mgrit_plan_set_coarse_solver")
 
     @property
     def nc(self):

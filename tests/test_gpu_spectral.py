@@ -1,0 +1,80 @@
+"""Spectral solve of the coarsest level (MGRIT_COARSE_SPECTRAL) on the GPU.
+
+The coarsest system x^s = Psi x^(s-1) + g^s is solved per Fourier mode of
+the circulant Psi instead of step by step.  In exact arithmetic the two are
+the same solve, so MGRIT must take the same iterations with residual
+histories equal to rounding, and converge to the oracle's sequential
+stepping.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import rk
+from paper_1910_03726_amd import inputs, mgrit as M
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # scheme, nx, nt, m, levels, cycle, precision
+    ("ERK3", 1024, 4096, 4, 3, "V", "fp64"),
+    ("ERK1", 256, 4096, 4, 4, "V", "fp64"),
+    ("ERK5", 2048, 2048, 8, 3, "F", "fp64"),
+    ("SDIRK3", 512, 2048, 16, 2, "V", "fp64"),
+    ("ERK3", 8192, 1024, 4, 3, "V", "fp64"),
+    ("ERK5", 1024, 4096, 8, 3, "V", "fp32"),
+]
+
+
+def _plan(scheme, nx, nt, m, levels, cycle, precision, coarse):
+    c = rk.paper_cfl(scheme) if scheme.startswith("ERK") else 4.0
+    psi, _ = M.psi_optimize(scheme, c, nx, m, levels)
+    return M.Plan(nx, nt, c, scheme, m, levels, psi, cycle=cycle, precision=precision,
+                  coarse=coarse), c
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}x{c[2]}-m{c[3]}-L{c[4]}-{c[6]}"
+                                             for c in CASES])
+def test_spectral_equals_sweep(case):
+    res = {}
+    for coarse in ("sweep", "spectral"):
+        P, _ = _plan(*case, coarse)
+        with P:
+            assert ("(spectral solve)" in P.describe()) == (coarse == "spectral")
+            u0 = torch.tensor(inputs.fourier_u0(case[1], 6, 3), device="cuda")
+            P.set_seed(17)
+            res[coarse] = P.solve(u0, None, tol=1e-10, maxit=60, out="final")
+    a, b = res["sweep"], res["spectral"]
+    assert a.status == b.status == M.OK
+    assert a.iters == b.iters
+    h0 = a.hist[0]
+    for x, y in zip(a.hist, b.hist):
+        assert abs(x - y) <= 1e-10 * h0 + 1e-6 * x
+    ua, ub = a.out.cpu().numpy(), b.out.cpu().numpy()
+    assert np.max(np.abs(ua - ub)) <= 1e-9 * np.max(np.abs(ua))
+
+
+@pytest.mark.parametrize("scheme,nx,nt,m,levels", [("ERK3", 512, 2048, 4, 3),
+                                                   ("SDIRK3", 256, 1024, 8, 2)])
+def test_spectral_solution_matches_sequential_stepping(scheme, nx, nt, m, levels):
+    P, c = _plan(scheme, nx, nt, m, levels, "V", "fp64", "spectral")
+    with P:
+        u0n = inputs.fourier_u0(nx, 6, 9)
+        r = P.solve(torch.tensor(u0n, device="cuda"), None, tol=1e-13, maxit=80, out="final")
+        assert r.status == M.OK
+    d = rk.Discretization(scheme, nx, c)
+    ref = d.propagate(u0n, nt)
+    got = r.out.cpu().numpy()[0]
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_spectral_needs_a_power_of_two():
+    c = rk.paper_cfl("ERK3")
+    psi, _ = M.psi_optimize("ERK3", c, 96, 4, 2)
+    with M.Plan(96, 384, c, "ERK3", 4, 2, psi) as P:
+        with pytest.raises(M.MgritError) as e:
+            P.set_coarse_solver("spectral")
+        assert e.value.code == M.EINVAL
+        P.set_coarse_solver("sweep")
+        assert "(spectral solve)" not in P.describe()
