@@ -247,8 +247,9 @@ int mgrit_solve_batch(int n, const mgrit_plan_t* plans,
 int mgrit_plan_set_coarse_solver(mgrit_plan_t plan, int mode);
 
 /* out[b] = Phi^k in[b] for b = 0..batch-1, rows of n_x values (device,
- * row-major, in and out may not overlap).  The fine stepper of the plan in
- * the plan's precision of relaxation; asynchronous on the plan stream. */
+ * row-major, in and out may not overlap; k = 0 copies).  The fine stepper
+ * of the plan in the plan's precision of relaxation; asynchronous on the
+ * plan stream.  batch = 0 does nothing (in and out may then be NULL). */
 int phi_apply_batch(mgrit_plan_t plan, const double* in_dev, double* out_dev,
                     int batch, int ksteps);
 

@@ -1129,8 +1129,9 @@ const char* mgrit_plan_describe(mgrit_plan_t plan) {
 
 int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
                     int ksteps) {
-  if (!plan || !in || !out || batch < 0 || ksteps < 0) return MGRIT_EINVAL;
-  if (batch == 0) return MGRIT_OK;
+  if (!plan || batch < 0 || ksteps < 0) return MGRIT_EINVAL;
+  if (batch == 0) return MGRIT_OK;  // nothing to do (the rows may be NULL)
+  if (!in || !out) return MGRIT_EINVAL;
   Plan* P = reinterpret_cast<Plan*>(plan);
   const OpDesc& op = P->lev[0].op;
   RelaxArgs a = base_args(*P, op);
