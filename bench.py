@@ -42,8 +42,7 @@ TOL = 1e-10
 
 def _plan(w, precision=None):
     from paper_1910_03726_amd import mgrit as M
-    psi, mi = M.psi_optimize(w["scheme"], w["cfl"], w["nx"], w["m"], w["levels"],
-                             rule=w["psi_rule"], widths=w["psi_widths"])
+    psi, mi = M.workload_psi(w)
     P = M.Plan(w["nx"], w["nt"], w["cfl"], w["scheme"], w["m"], w["levels"], psi,
                cycle=w["cycle"], precision=precision or w["precision"])
     return P, psi
@@ -266,14 +265,17 @@ def _auto_levels(nt, m):
     return L
 
 
-def workload_line(name, steps, warmup, torch, precision=None):
+def workload_line(name, steps, warmup, torch, precision=None, psi_rule=None):
     from paper_1910_03726_amd import inputs
     w = dict(inputs.WORKLOADS[name])
+    if psi_rule:
+        w["psi_rule"] = psi_rule
     P, psi = _plan(w, precision)
     u0, uinit = _inputs(w, torch)
     dt, r = _timed_solves(P, u0, uinit, steps, warmup, torch)
     st = r.stats
-    d = {"precision": precision or w["precision"], "ms_to_tol": round(dt * 1e3, 3),
+    d = {"precision": precision or w["precision"], "psi_rule": w["psi_rule"],
+         "ms_to_tol": round(dt * 1e3, 3),
          "dof_per_s": w["nx"] * w["nt"] / dt, "iterations": r.iters,
          "outer_iterations": st.outer_iterations, "final_residual": r.hist[-1],
          "fine_passes_fp64": st.fine_passes_fp64, "fine_passes_fp32": st.fine_passes_fp32,
@@ -345,7 +347,7 @@ def main():
             "config": {"workload": a.workload, "scheme": w["scheme"], "nx": w["nx"],
                        "nt": w["nt"], "cfl": w["cfl"], "m": w["m"],
                        "levels": w["levels"], "cycle": w["cycle"], "tol": TOL,
-                       "psi_nnz": [len(o) for o, _ in psi]},
+                       "psi_rule": w["psi_rule"], "psi_nnz": [len(o) for o, _ in psi]},
             "iterations": r.iters, "final_residual": r.hist[-1],
             "step_ms": {"median": round(1e3 * float(np.median(each)), 4),
                         "p95": round(1e3 * float(np.percentile(each, 95)), 4),
@@ -359,6 +361,9 @@ def main():
     P.close()
     if not a.no_extra:
         extra = {}
+        if w["psi_rule"] == "bound":  # the same solve with the Sec. 4.4 width rule
+            extra[a.workload + "@window_rule"] = workload_line(a.workload, 3, 1, torch,
+                                                               psi_rule="window")
         for name in inputs.WORKLOADS:
             if name == a.workload:
                 continue

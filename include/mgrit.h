@@ -172,6 +172,27 @@ int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels,
                        int rule, const int* widths, double eta,
                        mgrit_taps* out, double* max_imag);
 
+/* ERK coarse operators with windows chosen by the two-level convergence
+ * bound of Sec. 3 (eq. (7)): level by level (Psi_{l+1} against
+ * Phi_l^m, Sec. 4.4), the contiguous window of phi~^m placed as for
+ * MGRIT_PSI_WINDOW, its width the narrowest from the window rule's width up
+ * to MGRIT_PSI_BOUND_MAX_WIDTH (the widest register-resident stencil of the
+ * relaxation kernels) whose bound
+ *     max_k sqrt(m) |lambda_k|^m |lambda_k^m - mu_k| sum_{j < n_l/m - 1} |mu_k|^j
+ * (n_l the steps of level l, n_1 = nt) is at most `target`, else the width
+ * with the smallest bound.  Wider coarse stencils cost the relaxation
+ * kernels little (their passes are bound by memory traffic and latency) and
+ * save iterations.  Each candidate width is one weighted least-squares
+ * solve (eq. (9)), so this setup takes tens of milliseconds per level at
+ * n_x = 8192.  out as for mgrit_psi_optimize (room for up to
+ * MGRIT_PSI_BOUND_MAX_WIDTH taps per level); bounds (may be NULL) receives
+ * the bound of each level's choice.  SDIRK schemes: MGRIT_EINVAL (their
+ * patterns are thresholded, Sec. 4.6).  Host only. */
+#define MGRIT_PSI_BOUND_MAX_WIDTH 64
+int mgrit_psi_optimize_bound(int scheme, double cfl, int nx, int nt, int m,
+                             int levels, double target, mgrit_taps* out,
+                             double* bounds, double* max_imag);
+
 /* ---- plans and solves (GPU) --------------------------------------------- */
 
 /* Create a plan for n_x, n_t, alpha, Courant number c, scheme, coarsening

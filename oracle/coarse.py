@@ -207,3 +207,70 @@ def two_level_bound(lam, mu, m, nt):
     am = np.abs(mu)
     return (np.sqrt(m) * np.abs(lam) ** m * np.abs(lam ** m - mu) / (1.0 - am)
             * (1.0 - am ** (nt / m - 1)))
+
+
+# ---------------------------------------------------------------------------
+# Bound-driven window widths (eq. (7) per level)
+# ---------------------------------------------------------------------------
+def geometric_sum(a, N):
+    """sum_{j<N} a^j elementwise: the factor (1 - a^N)/(1 - a) of eq. (7),
+    written so that a = 1 (where it equals N) needs no 0/0: within 1e-12 of
+    1 the first-order expansion N + N(N-1)/2 (a - 1)."""
+    a = np.asarray(a, dtype=float)
+    out = N + 0.5 * N * (N - 1.0) * (a - 1.0)
+    far = np.abs(1.0 - a) >= 1e-12
+    with np.errstate(divide="ignore"):
+        out[far] = np.expm1(N * np.log(a[far])) / (a[far] - 1.0)
+    return out
+
+
+def max_two_level_bound(lam, mu, m, nt):
+    """max over the modes of eq. (7) for a level of nt steps; inf if any
+    mode's value is not finite."""
+    lam = np.asarray(lam)
+    mu = np.asarray(mu)
+    v = (np.sqrt(m) * np.abs(lam) ** m * np.abs(lam ** m - mu)
+         * geometric_sum(np.abs(mu), nt // m - 1))
+    return float(np.max(v)) if np.all(np.isfinite(v)) else float("inf")
+
+
+def build_hierarchy_bound(disc, m, levels, nt, target=1e-3, max_width=64):
+    """ERK coarse operators Psi_2..Psi_L with bound-driven windows.
+
+    Level by level (Psi_{l+1} against Phi_l^m, Sec. 4.4) the contiguous
+    window of phi~^m is placed as by the window rule (best_window), and its
+    width is the narrowest from the window rule's width up to max_width for
+    which max_two_level_bound(lambda_l, mu, m, n_l) <= target (n_l the steps
+    of level l, n_1 = nt); if none reaches the target, the width with the
+    smallest bound (the first on ties).  Returns dicts as build_hierarchy,
+    with the level's "bound".
+    """
+    n = disc.nx
+    lam = disc.eigenvalues()
+    nnz_prev = fine_nnz(disc)
+    nl = nt
+    out = []
+    for _ in range(1, levels):
+        col, _ = phi_m_first_column(lam, m)
+        w0 = window_rule_width(col, nnz_prev)
+        best = None
+        pick = None
+        for width in range(w0, max(w0, min(max_width, n)) + 1):
+            offs = best_window(col, width)
+            psi, im = lsq_psi(lam, m, offs)
+            mu = taps_eigenvalues(offs, psi, n)
+            b = max_two_level_bound(lam, mu, m, nl)
+            cand = {"offsets": np.asarray(offs), "weights": psi, "max_imag": im,
+                    "eigs": mu, "bound": b}
+            if b <= target:
+                pick = cand
+                break
+            if best is None or b < best["bound"]:
+                best = cand
+        pick = pick if pick is not None else best
+        out.append(pick)
+        lam = pick["eigs"]
+        nnz_prev = len(pick["offsets"])
+        nl //= m
+    return out
+

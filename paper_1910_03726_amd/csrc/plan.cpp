@@ -890,6 +890,38 @@ int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels, int ru
   return rc;
 }
 
+int mgrit_psi_optimize_bound(int scheme, double cfl, int nx, int nt, int m, int levels,
+                             double target, mgrit_taps* out, double* bounds,
+                             double* max_imag) {
+  if (!out) return MGRIT_EINVAL;
+  std::vector<Taps> h;
+  std::vector<double> b;
+  double mi = 0.0;
+  int rc;
+  try {
+    rc = psi_hierarchy_bound(scheme, cfl, nx, nt, m, levels, target, MGRIT_PSI_BOUND_MAX_WIDTH, h,
+                             b, mi);
+  } catch (...) {
+    return MGRIT_ENOMEM;
+  }
+  if (rc != MGRIT_OK && rc != MGRIT_EIMAG) return rc;
+  if (max_imag) *max_imag = mi;
+  for (int l = 0; l < levels - 1; ++l) {
+    const Taps& t = h[l];
+    if ((int)t.off.size() > out[l].nnz || !out[l].offset || !out[l].weight) {
+      out[l].nnz = (int)t.off.size();
+      return MGRIT_ECAPACITY;
+    }
+    out[l].nnz = (int)t.off.size();
+    for (size_t i = 0; i < t.off.size(); ++i) {
+      out[l].offset[i] = t.off[i];
+      out[l].weight[i] = t.w[i];
+    }
+    if (bounds) bounds[l] = b[l];
+  }
+  return rc;
+}
+
 
 int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
                       int scheme, int m, int levels, const mgrit_taps* psi, int cycle,

@@ -628,6 +628,107 @@ int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
   return max_imag > 1e-8 ? MGRIT_EIMAG : MGRIT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Bound-driven windows: eq. (7) per mode, the window width chosen per level
+// ---------------------------------------------------------------------------
+// sum_{j < N} a^j, evaluated without cancellation near a = 1
+// sum_{j<N} a^j; within 1e-12 of a = 1 its first-order expansion
+// N + N(N-1)/2 (a-1), whose next term is below rounding there
+static double geometric_sum(double a, double N) {
+  if (std::fabs(1.0 - a) < 1e-12) return N + 0.5 * N * (N - 1.0) * (a - 1.0);
+  return std::expm1(N * std::log(a)) / (a - 1.0);
+}
+
+double two_level_bound_max(const std::vector<cd>& lam, const std::vector<cd>& mu, int m,
+                           long long nt) {
+  const double N = (double)(nt / m) - 1.0;
+  double b = 0.0;
+  for (size_t k = 0; k < lam.size(); ++k) {
+    const double am = std::abs(mu[k]);
+    const double v = std::sqrt((double)m) * std::pow(std::abs(lam[k]), m) *
+                     std::abs(ipow(lam[k], m) - mu[k]) * geometric_sum(am, N);
+    if (!std::isfinite(v)) return HUGE_VAL;  // overflow: never a choice
+    b = std::max(b, v);
+  }
+  return b;
+}
+
+int psi_hierarchy_bound(int scheme, double cfl, int nx, int nt, int m, int levels,
+                        double target, int max_width, std::vector<Taps>& out,
+                        std::vector<double>& bounds, double& max_imag) {
+  Tableau t;
+  if (!get_tableau(scheme, t) || t.implicit) return MGRIT_EINVAL;
+  if (nx < 2 || nt < 1 || m < 2 || levels < 2 || !(cfl > 0.0) || !(target > 0.0) ||
+      max_width < 1)
+    return MGRIT_EINVAL;
+  long long span = 1;
+  for (int l = 1; l < levels; ++l) span *= m;
+  if (span > nt || nt % span) return MGRIT_EINVAL;
+  out.clear();
+  bounds.clear();
+  max_imag = 0.0;
+  std::vector<cd> lam(nx);
+  {
+    std::vector<int> off;
+    std::vector<double> d;
+    upwind(t.p, off, d);
+    for (int k = 0; k < nx; ++k) {
+      const double th = 2.0 * kPi * k / nx;
+      cd z = 0.0;
+      for (size_t j = 0; j < off.size(); ++j) z += d[j] * std::exp(cd(0.0, off[j] * th));
+      lam[k] = stability(t, -cfl * z);
+    }
+  }
+  Taps f;
+  erk_taps(t, cfl, nx, f);
+  int nnz_prev = (int)f.off.size();
+  long long n = nt;
+  for (int l = 1; l < levels; ++l) {
+    std::vector<cd> col(nx);
+    for (int k = 0; k < nx; ++k) col[k] = ipow(lam[k], m);
+    dft(col, true);
+    std::vector<double> rcol(nx);
+    for (int k = 0; k < nx; ++k) rcol[k] = col[k].real();
+    const int w0 = std::max(nnz_prev, cyclic_span(threshold(rcol, 0.02), nx));
+    const int w1 = std::max(w0, std::min(max_width, nx));
+    Taps best, pick;
+    std::vector<cd> best_mu, pick_mu;
+    double best_b = 0.0, pick_b = 0.0;
+    bool have_best = false, have_pick = false;
+    for (int W = w0; W <= w1 && !have_pick; ++W) {
+      Taps tp;
+      tp.off = best_window(rcol, W);
+      max_imag = std::max(max_imag, lsq_psi(lam, m, tp.off, tp.w));
+      std::vector<cd> mu;
+      taps_eigs(tp, nx, mu);
+      const double b = two_level_bound_max(lam, mu, m, n);
+      if (b <= target) {
+        pick = tp;
+        pick_mu.swap(mu);
+        pick_b = b;
+        have_pick = true;
+      } else if (!have_best || b < best_b) {
+        best = tp;
+        best_mu.swap(mu);
+        best_b = b;
+        have_best = true;
+      }
+    }
+    if (!have_pick) {
+      if (!have_best) return MGRIT_EINVAL;
+      pick = best;
+      pick_mu.swap(best_mu);
+      pick_b = best_b;
+    }
+    nnz_prev = (int)pick.off.size();
+    lam.swap(pick_mu);
+    out.push_back(pick);
+    bounds.push_back(pick_b);
+    n /= m;
+  }
+  return max_imag > 1e-8 ? MGRIT_EIMAG : MGRIT_OK;
+}
+
 void tap_window(const Taps& t, int nx, int& omin, int& W, std::vector<double>& dense) {
   std::map<int, double> f;
   for (size_t q = 0; q < t.off.size(); ++q) f[((t.off[q] % nx) + nx) % nx] += t.w[q];

@@ -58,6 +58,18 @@ double lsq_psi(const std::vector<cd>& lam, int m, const std::vector<int>& offs,
                std::vector<double>& w);
 
 // The coarse hierarchy of mgrit_psi_optimize (see mgrit.h).
+// Eq. (7) maximised over the modes: the two-level FCF bound of the pair
+// (eigenvalues lam of Phi_l, mu of Psi) on a level of nt steps.
+double two_level_bound_max(const std::vector<cd>& lam, const std::vector<cd>& mu, int m,
+                           long long nt);
+
+// ERK coarse operators whose contiguous windows are as narrow as the two-
+// level bound allows: per level the narrowest width from the window rule's
+// up to max_width with bound <= target, or the width with the smallest bound.
+int psi_hierarchy_bound(int scheme, double cfl, int nx, int nt, int m, int levels,
+                        double target, int max_width, std::vector<Taps>& out,
+                        std::vector<double>& bounds, double& max_imag);
+
 int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
                   const int* widths, double eta, std::vector<Taps>& out,
                   double& max_imag);

@@ -67,6 +67,9 @@ def erk_cfl(p, fraction=0.85):
 
 
 # The four single-solve workloads (sizes, scheme, solver shape, seeds).
+# psi_rule: "window" (contiguous window, Sec. 4.4 width rule, or psi_widths),
+# "eta" (SDIRK thresholding, Sec. 4.6), "bound" (window widths chosen per
+# level until the eq. (7) bound reaches psi_target).
 WORKLOADS = {
     "erk1_u1_nx64_nt256_m4_2level": dict(
         scheme="ERK1", nx=64, nt=256, cfl=erk_cfl(1), m=4, levels=2,
@@ -74,7 +77,7 @@ WORKLOADS = {
         u0=dict(nmodes=4, decay=0.0, seed=0), init_seed=1),
     "erk3_u3_nx4096_nt16384_m8_fcycle": dict(
         scheme="ERK3", nx=4096, nt=16384, cfl=erk_cfl(3), m=8, levels=4,
-        cycle="F", precision="fp64", psi_rule="window", psi_widths=None,
+        cycle="F", precision="fp64", psi_rule="bound", psi_widths=None, psi_target=1e-3,
         u0=dict(nmodes=8, decay=2.0, seed=0), init_seed=1),
     "sdirk3_u3_nx2048_nt8192_m16_2level": dict(
         scheme="SDIRK3", nx=2048, nt=8192, cfl=4.0, m=16, levels=2,
@@ -82,7 +85,7 @@ WORKLOADS = {
         u0=dict(nmodes=8, decay=0.0, seed=0), init_seed=1),
     "erk5_u5_nx8192_nt65536_m8_fp32relax": dict(
         scheme="ERK5", nx=8192, nt=65536, cfl=erk_cfl(5), m=8, levels=5,
-        cycle="V", precision="fp32", psi_rule="window", psi_widths=None,
+        cycle="V", precision="fp32", psi_rule="bound", psi_widths=None, psi_target=1e-3,
         u0=dict(nmodes=16, decay=0.0, seed=0), init_seed=1),
 }
 

@@ -128,6 +128,8 @@ _SIGS = {
                             ctypes.POINTER(_I)]),
     "mgrit_psi_optimize": (_I, [_I, _D, _I, _I, _I, _I, ctypes.POINTER(_I), _D,
                                 ctypes.POINTER(Taps), ctypes.POINTER(_D)]),
+    "mgrit_psi_optimize_bound": (_I, [_I, _D, _I, _I, _I, _I, _D, ctypes.POINTER(Taps),
+                                      ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mgrit_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _I, _I, _I,
                                ctypes.POINTER(Taps), _I, _I, _I, _P]),
     "mgrit_solve": (_I, [_P, _P, _P, _D, _I, _P, _I, ctypes.POINTER(_D),
@@ -235,6 +237,43 @@ def psi_optimize(scheme, cfl, nx, m, levels, rule="auto", widths=None, eta=0.0,
         n = arr[i].nnz
         out.append((np.array(bufs[i][0][:n]), np.array(bufs[i][1][:n])))
     return out, mi.value
+
+
+def psi_optimize_bound(scheme, cfl, nx, nt, m, levels, target=1e-3):
+    """Coarse operators with bound-driven window widths
+    (mgrit_psi_optimize_bound): list of (offsets, weights), the bound of
+    each level's choice, max_imag."""
+    cap = 64
+    bufs = []
+    arr = (Taps * (levels - 1))()
+    for i in range(levels - 1):
+        o = (_I * cap)()
+        w = (_D * cap)()
+        bufs.append((o, w))
+        arr[i].nnz = cap
+        arr[i].offset = o
+        arr[i].weight = w
+    bounds = (_D * (levels - 1))()
+    mi = _D()
+    rc = lib().mgrit_psi_optimize_bound(_scheme(scheme), cfl, nx, nt, m, levels, target, arr,
+                                        bounds, ctypes.byref(mi))
+    _check(rc, "mgrit_psi_optimize_bound")
+    out = []
+    for i in range(levels - 1):
+        n = arr[i].nnz
+        out.append((np.array(bufs[i][0][:n]), np.array(bufs[i][1][:n])))
+    return out, list(bounds), mi.value
+
+
+def workload_psi(w):
+    """The coarse operators of a workload description (inputs.WORKLOADS):
+    (list of (offsets, weights), max_imag)."""
+    if w["psi_rule"] == "bound":
+        psi, _, mi = psi_optimize_bound(w["scheme"], w["cfl"], w["nx"], w["nt"], w["m"],
+                                        w["levels"], w["psi_target"])
+        return psi, mi
+    return psi_optimize(w["scheme"], w["cfl"], w["nx"], w["m"], w["levels"],
+                        rule=w["psi_rule"], widths=w["psi_widths"])
 
 
 def _ptr(t, name, numel=None):

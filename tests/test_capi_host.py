@@ -104,6 +104,29 @@ def test_psi_optimize_matches_oracle(scheme, nx, m, L, rule, widths):
         assert np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("scheme,nx,nt,m,L,target", [("ERK3", 256, 4096, 4, 4, 1e-3),
+                                                      ("ERK5", 128, 2048, 8, 3, 1e-3),
+                                                      ("ERK1", 64, 2048, 4, 3, 1e-4)])
+def test_psi_optimize_bound_matches_oracle(scheme, nx, nt, m, L, target):
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    got, bounds, mi = M.psi_optimize_bound(scheme, c, nx, nt, m, L, target)
+    H = coarse.build_hierarchy_bound(d, m, L, nt, target)
+    assert mi < 1e-8
+    for (o, w), b, h in zip(got, bounds, H):
+        assert sorted(o.tolist()) == sorted(h["offsets"].tolist())
+        a = w[np.argsort(o)]
+        ref = h["weights"][np.argsort(h["offsets"])]
+        assert np.max(np.abs(a - ref)) <= 1e-8 * np.max(np.abs(ref))
+        # a bound at rounding level (|lambda^m - mu| ~ eps) differs by rounding
+        assert b == pytest.approx(h["bound"], rel=1e-6, abs=1e-10)
+
+
+def test_psi_optimize_bound_rejects_sdirk():
+    with pytest.raises(M.MgritError):
+        M.psi_optimize_bound("SDIRK3", 4.0, 256, 1024, 4, 2)
+
+
 def test_psi_redisc_is_erk_at_m_times_c():
     c = rk.paper_cfl("ERK1")
     got, _ = M.psi_optimize("ERK1", c, 64, 4, 3, rule="redisc")

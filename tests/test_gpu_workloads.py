@@ -16,10 +16,11 @@ from paper_1910_03726_amd import inputs, mgrit as M
 pytestmark = pytest.mark.gpu
 
 
-def _run(name, precision=None, tol=1e-13, maxit=60):
+def _run(name, precision=None, tol=1e-13, maxit=60, psi_rule=None):
     w = dict(inputs.WORKLOADS[name])
-    psi, mi = M.psi_optimize(w["scheme"], w["cfl"], w["nx"], w["m"], w["levels"],
-                             rule=w["psi_rule"], widths=w["psi_widths"])
+    if psi_rule:
+        w["psi_rule"] = psi_rule
+    psi, mi = M.workload_psi(w)
     assert mi < 1e-8
     u0 = inputs.workload_u0(w)
     nc = w["nt"] // w["m"]
@@ -70,3 +71,17 @@ def test_paper_iteration_counts():
     assert r.iters == 6
     _, _, r, _, _ = _run("sdirk3_u3_nx2048_nt8192_m16_2level", tol=1e-10)
     assert r.iters == 4
+
+
+@pytest.mark.parametrize("name", ["erk3_u3_nx4096_nt16384_m8_fcycle",
+                                  "erk5_u5_nx8192_nt65536_m8_fp32relax"])
+def test_bound_rule_beats_the_width_rule(name):
+    # windows widened until the eq. (7) bound reaches 1e-3 need fewer
+    # iterations than the Sec. 4.4 width rule, to the same solution
+    wb, u0, rb, Cb, _ = _run(name, tol=1e-10, psi_rule="bound")
+    ww, _, rw, Cw, _ = _run(name, tol=1e-10, psi_rule="window")
+    print(name, "bound", rb.iters, "window", rw.iters)
+    assert rb.converged and rw.converged
+    assert rb.iters < rw.iters
+    assert _rel(Cb[-1], Cw[-1]) < 1e-6
+

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import coarse, mgrit, rk
+from paper_1910_03726_amd import inputs
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                    "paper_tables.json")))
@@ -155,3 +156,68 @@ def test_two_level_bound_eq7_brute_force(lam, dmu, m):
 def test_bound_vanishes_for_ideal_psi():
     lam = 0.9 * np.exp(0.4j)
     assert coarse.two_level_bound(lam, lam ** 4, 4, 64) == 0.0
+
+
+# -- bound-driven window widths ---------------------------------------------
+def test_geometric_sum_is_the_eq7_factor():
+    a = np.array([0.0, 0.3, 0.999, 1.0, 1.0 + 1e-13, 1.02])
+    N = 37
+    g = coarse.geometric_sum(a, N)
+    brute = np.array([sum(x ** j for j in range(N)) for x in a])
+    assert np.allclose(g, brute, rtol=1e-12, atol=0)
+    # away from 1 it is the ratio written in eq. (7)
+    far = np.abs(1 - a) > 1e-6
+    assert np.allclose(g[far], (1 - a[far] ** N) / (1 - a[far]), rtol=1e-12)
+
+
+def test_max_bound_is_the_largest_eq7_term():
+    rng = np.random.default_rng(3)
+    lam = 0.98 * np.exp(2j * np.pi * rng.random(50))
+    mu = lam ** 4 * (1 + 0.01 * rng.standard_normal(50))
+    mu *= 0.999 / np.max(np.abs(mu))
+    b = coarse.max_two_level_bound(lam, mu, 4, 256)
+    assert b == pytest.approx(np.max(coarse.two_level_bound(lam, mu, 4, 256)), rel=1e-12)
+
+
+@pytest.mark.parametrize("scheme,nx,nt,m,L,target", [("ERK3", 64, 1024, 4, 3, 1e-3),
+                                                      ("ERK5", 64, 512, 8, 2, 1e-2),
+                                                      ("ERK1", 32, 1024, 4, 3, 1e-4)])
+def test_bound_rule_takes_the_narrowest_window_meeting_the_target(scheme, nx, nt, m, L, target):
+    d = rk.Discretization(scheme, nx, rk.paper_cfl(scheme))
+    H = coarse.build_hierarchy_bound(d, m, L, nt, target)
+    lam = d.eigenvalues()
+    nnz_prev = coarse.fine_nnz(d)
+    nl = nt
+    for h in H:
+        col, _ = coarse.phi_m_first_column(lam, m)
+        w0 = coarse.window_rule_width(col, nnz_prev)
+        widths = list(range(w0, max(w0, min(64, nx)) + 1))
+        bounds = []
+        for wdt in widths:
+            offs = coarse.best_window(col, wdt)
+            psi, _ = coarse.lsq_psi(lam, m, offs)
+            mu = coarse.taps_eigenvalues(offs, psi, nx)
+            bounds.append(float(np.max(coarse.two_level_bound(lam, mu, m, nl))))
+        ok = [wd for wd, b in zip(widths, bounds) if b <= target]
+        want = ok[0] if ok else widths[int(np.argmin(bounds))]
+        assert len(h["offsets"]) == want
+        assert h["bound"] == pytest.approx(bounds[widths.index(want)], rel=1e-9)
+        lam = h["eigs"]
+        nnz_prev = want
+        nl //= m
+
+
+def test_bound_rule_needs_fewer_iterations_than_the_window_rule():
+    s, nx, nt, m = "ERK3", 64, 1024, 4
+    d = rk.Discretization(s, nx, rk.paper_cfl(s))
+    u0 = np.sin(np.pi * d.x) ** 4
+    uinit = inputs.random_iterate(nt // m + 1, nx, 1)
+    its = {}
+    for name, H in (("window", coarse.build_hierarchy(d, m, 3)),
+                    ("bound", coarse.build_hierarchy_bound(d, m, 3, nt, 1e-3))):
+        ops = [d.step] + [mgrit.taps_op(h["offsets"], h["weights"]) for h in H]
+        res = mgrit.MGRIT(ops, m, nt).solve(u0, uinit, 1e-10, 50, mgrit.norm_scale(d))
+        assert res.status == "converged"
+        its[name] = res.iters
+    assert its["bound"] < its["window"]
+
