@@ -21,10 +21,13 @@ plain, slow and meant to be checked by eye against the paper:
 * ``mgrit``  -- two-level and multilevel MGRIT (F or FCF relaxation,
                 V- or F-cycles) as described in Sec. 2.2 and Sec. 4.4,
                 with the discrete L2 residual stopping test.
+* ``inflow`` -- ERK+U with inflow/outflow boundaries (Sec. 4.5): inflow
+                ghosts by inverse Lax-Wendroff, stage boundary data,
+                outflow extrapolation, the truncated periodic Psi.
 
 Pins (tests under ``tests/test_oracle_*.py``) tie each function to values
 or identities the paper and the mathematics fix.  Functions whose output no
 such pin fixes say "parity unpinned" in their docstring.
 """
 
-from . import rk, coarse, mgrit  # noqa: F401
+from . import rk, coarse, mgrit, inflow  # noqa: F401

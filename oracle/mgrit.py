@@ -40,7 +40,7 @@ class Result:
 
 
 def _rhs(g, s, m, nc):
-    """g^{jm+s} for j = 0..nc-1 (None means the fine level: g^n = 0, n>0)."""
+    """g^{jm+s} for j = 0..nc-1 (None: g^n = 0 for n > 0)."""
     if g is None:
         return 0.0
     return g[s:s + nc * m:m]
@@ -143,17 +143,20 @@ class MGRIT:
         return f_interpolate(self.ops[l], v + e, g, m)
 
     # -- the solver ----------------------------------------------------------
-    def solve(self, u0, uinit, tol, maxit, norm_scale):
+    def solve(self, u0, uinit, tol, maxit, norm_scale, g=None):
         """Iterate from C-points ``uinit`` (row 0 replaced by u0).
 
         Returns Result with the FCF-relaxed C-points whose residual passed
-        the test (or the last ones).  ``norm_scale`` = sqrt(dx dt).
+        the test (or the last ones).  ``norm_scale`` = sqrt(dx dt).  ``g``:
+        the fine level's right-hand side rows g^0..g^{n_t} of eq. (3) (row 0
+        unused, u0 takes its place); None for g^n = 0, n > 0 (periodic
+        problems; inflow data make it nonzero, Sec. 4.5).
         """
         u = np.array(uinit, dtype=float, copy=True)
         u[0] = u0
         hist = []
         for it in range(maxit + 1):
-            v, r = self._pre(0, u, None)
+            v, r = self._pre(0, u, g)
             res = norm_scale * float(np.sqrt(np.sum(r * r)))
             hist.append(res)
             if not np.isfinite(res):
@@ -166,10 +169,10 @@ class MGRIT:
             u = v + e
         raise AssertionError("unreachable")
 
-    def fill(self, cpoints):
-        """All n_t+1 time levels from C-points by F-relaxation (fine level)."""
+    def fill(self, cpoints, g=None):
+        """All n_t+1 time levels from C-points by F-relaxation (fine level,
+        right-hand side ``g`` as in solve)."""
         nc = cpoints.shape[0] - 1
-        g = None
         return f_interpolate(self.ops[0], cpoints, g, self.m) if nc > 0 else cpoints
 
 

@@ -37,6 +37,34 @@ def sin4(nx):
     return np.sin(np.pi * grid(nx)) ** 4
 
 
+def inflow_grid(nx):
+    """Unknowns of the inflow/outflow problem: x_i = -1 + i dx, i = 1..n_x."""
+    return -1.0 + (2.0 / nx) * np.arange(1, nx + 1)
+
+
+def sin4_inflow_derivs(nt, dt, nderiv, t0=0.0):
+    """Inflow data g(t) = sin^4(pi t) at x = -1: row n holds g^(d)(t0 + n dt),
+    d = 0..nderiv-1, n = 0..nt-1 (sin^4 = 3/8 - cos(2 pi t)/2 + cos(4 pi t)/8)."""
+    t = t0 + dt * np.arange(nt)
+    out = np.empty((nt, nderiv))
+    for d in range(nderiv):
+        ph = d * np.pi / 2
+        v = (-0.5 * (2 * np.pi) ** d * np.cos(2 * np.pi * t + ph)
+             + 0.125 * (4 * np.pi) ** d * np.cos(4 * np.pi * t + ph))
+        out[:, d] = v + (0.375 if d == 0 else 0.0)
+    return out
+
+
+def poly_inflow_derivs(coeffs, nt, dt, nderiv):
+    """Inflow data g(t) = sum_k coeffs[k] t^k: row n holds g^(d)(n dt)."""
+    t = dt * np.arange(nt)
+    out = np.zeros((nt, nderiv))
+    for d in range(nderiv):
+        for k in range(d, len(coeffs)):
+            out[:, d] += coeffs[k] * (np.prod(np.arange(k - d + 1, k + 1)) if d else 1.0) * t ** (k - d)
+    return out
+
+
 def random_iterate(npoints, nx, seed):
     """U[0,1) values for ``npoints`` time levels (row 0 is replaced by u0)."""
     return np.random.default_rng(seed).random((npoints, nx))
