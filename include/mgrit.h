@@ -208,6 +208,39 @@ int mgrit_plan_create(mgrit_plan_t* plan, int nx, int nt, double alpha,
                       const mgrit_taps* psi, int cycle, int relax,
                       int precision, void* hip_stream);
 
+/* A plan for inflow/outflow boundaries (Sec. 4.5): u_t + alpha u_x = 0 on
+ * (-1, 1] with u(-1, t) = g(t), ERK schemes only, FP64 only.
+ *   Grid: unknowns at x_i = -1 + i dx, i = 1..n_x, dx = 2/n_x (u0 and all
+ *         outputs hold these n_x values); dt = c dx / alpha.
+ *   Fine step: ERKp+Up with outflow ghosts from the degree p-1 polynomial
+ *         through the last p unknowns, and inflow ghosts from a Taylor series
+ *         about x = -1 whose space derivatives the PDE turns into time
+ *         derivatives (inverse Lax-Wendroff), with stage-consistent boundary
+ *         data for every ERK stage; the step is u^{n+1} = Phi u^n + f^{n+1}.
+ *   inflow: host, n_t rows of n_derivs >= p+1 values, row n holding
+ *         g(t_n), g'(t_n), ..., g^(p)(t_n) at t_n = n dt (further columns
+ *         ignored); copied into the plan as the per-step forcing.
+ *   psi:  the periodic coarse stencils (as for mgrit_plan_create), applied
+ *         truncated to the interval (terms with i - offset outside 0..n_x-1
+ *         dropped; offsets taken in (-n_x/2, n_x/2]).
+ * The coarsest level is swept (no spectral solve: Psi is not circulant).
+ * phi_apply_batch on such a plan steps every row from t = 0 with the
+ * plan's inflow data (k <= n_t).  Other arguments and errors as
+ * mgrit_plan_create; n_x up to 10232 (two FP64 rows in a CU's 160 KB of
+ * LDS). */
+int mgrit_plan_create_inflow(mgrit_plan_t* plan, int nx, int nt, double alpha,
+                             double cfl, int scheme, int m, int levels,
+                             const mgrit_taps* psi, int cycle, int relax,
+                             const double* inflow, int n_derivs,
+                             void* hip_stream);
+
+/* The fine step of mgrit_plan_create_inflow's problem as its kernels apply
+ * it: phi (may be NULL) receives Phi as a dense n_x x n_x row-major matrix,
+ * B (may be NULL) the n_x x (p+1) matrix with f^{n+1} = B (g^(d)(t_n))_d,
+ * *n_derivs the p+1 columns of B.  Host only (for checks). */
+int mgrit_inflow_operator(int scheme, double cfl, double alpha, int nx,
+                          double* phi, double* B, int* n_derivs);
+
 /* Solve the space-time system to sqrt(dx dt sum r^2) <= tol (Sec. 2.2).
  *   u0_dev:    n_x initial values u^0 (device).
  *   uinit_dev: initial iterate at the C-points, (n_t/m + 1) x n_x (row 0 is

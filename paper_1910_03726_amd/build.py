@@ -36,6 +36,8 @@ def _jobs():
     objs.append((HIPCC, os.path.join(CSRC, "solve.cpp"), "solve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
     objs.append((HIPCC, os.path.join(CSRC, "spectral.hip"), "spectral.o", []))
+    objs.append((HIPCC, os.path.join(CSRC, "inst_bounded.hip"), "inst_bounded.o", []))
+    objs.append(("g++", os.path.join(CSRC, "inflow_setup.cpp"), "inflow_setup.o", []))
     for prec in (0, 1):
         objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),
                      f"inst_sdirk_{prec}.o", [f"-DMGR_PREC={prec}"]))

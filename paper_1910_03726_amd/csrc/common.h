@@ -41,10 +41,14 @@ struct RelaxArgs {
                            // out[j+out_off] - (in[j+1] + corr[j+1]), the
                            // update of C-point j+1 (row 0 set to 0)
   const double* taps;      // stencil: weights of the window offsets omin..omin+W-1
-  const int* tap_off;      // generic kernel: offsets in [0, nx)
-  const void* sdirk;       // SDIRK kernel: device SdirkDev
-  int ntaps;               // generic kernel: number of taps
-  int omin;                // stencil window start (frame shift per step), in [0, nx)
+  const int* tap_off;      // generic kernel: offsets in [0, nx); bounded
+                           // kernel: signed offsets
+  const void* opdata;      // SDIRK kernel: device SdirkDev; bounded kernel:
+                           // device BoundedDev
+  int ntaps;               // generic / bounded kernel: number of taps
+  int omin;                // stencil window start (frame shift per step), in
+                           // [0, nx); bounded kernel: steps between the start
+                           // times of consecutive blocks (inflow data rows)
   int mode, rhs_mode;
   int m;                   // fine steps per interval
   int nx;
@@ -70,6 +74,21 @@ struct BatchArgs {
   RelaxArgs a[kMaxBatch];
   int start[kMaxBatch];
   int n;  // members, 1..kMaxBatch
+};
+
+// Operator of a level with inflow/outflow boundaries (Sec. 4.5), applied by
+// the bounded kernel as
+//   (Phi u)_i = sum_c lblk[i*ncl + c] u_c                 for i < nl,
+//             = sum_c rblk[(i-nx+nr)*ncr + c] u_{nx-ncr+c}  for i >= nx - nr,
+//             = sum_t taps[t] u_{i - off[t]} over 0 <= i - off[t] < nx
+//                                                         otherwise,
+// plus, on the fine level, the inflow forcing of the step from t_n:
+// F[n*nf + i] added to rows i < nf (F: one row per fine step).
+struct BoundedDev {
+  int nl, ncl, nr, ncr, nf, pad_;
+  const double* lblk;
+  const double* rblk;
+  const double* F;
 };
 
 // One factor of a cyclic banded stage solve: a linear recurrence of order

@@ -13,6 +13,7 @@ MGR_DECL_K(1) MGR_DECL_K(2) MGR_DECL_K(4) MGR_DECL_K(8) MGR_DECL_K(16) MGR_DECL_
 #undef MGR_DECL_K
 void register_sdirk_0(KernelTable&);
 void register_sdirk_1(KernelTable&);
+void register_bounded(KernelTable&);
 
 int width_index(int W) {
   for (int i = 0; i < kNumWidths; ++i)
@@ -42,6 +43,7 @@ static KernelTable build_table() {
 #undef MGR_REG_K
   register_sdirk_0(t);
   register_sdirk_1(t);
+  register_bounded(t);
   return t;
 }
 

@@ -356,6 +356,49 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   return upload(&d_sdirk, &sd, sizeof(SdirkDev));
 }
 
+int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
+                         const std::vector<double>* F, int nx, int stride, std::string& err) {
+  const KernelTable& kt = kernel_table();
+  kind = OP_BOUNDED;
+  NL = 256;
+  fn[0] = kt.bounded;
+  bfn[0] = kt.bounded_b;
+  fn[1] = nullptr;  // FP64 state only
+  bfn[1] = nullptr;
+  shmem[0] = shmem[1] = (size_t)2 * nx * sizeof(double);
+  if (!fn[0] || shmem[0] > kernel_info(fn[0]).max_lds) {
+    err = "n_x too large for the bounded relaxation kernel";
+    return MGRIT_EINVAL;
+  }
+  nnz = (int)interior.off.size();
+  ntaps = nnz;
+  omin = stride;
+  int rc = upload((void**)&d_taps, interior.w.data(), interior.w.size() * sizeof(double));
+  if (!rc) rc = upload((void**)&d_off, interior.off.data(), interior.off.size() * sizeof(int));
+  if (rc) return rc;
+  BoundedDev bd;
+  std::memset(&bd, 0, sizeof bd);
+  auto put = [&](const std::vector<double>& h, const double** dst) {
+    if (h.empty()) return (int)MGRIT_OK;  // an empty block stays NULL
+    void* d = nullptr;
+    const int r = upload(&d, h.data(), h.size() * sizeof(double));
+    if (r) return r;
+    d_extra.push_back(d);
+    *dst = (const double*)d;
+    return MGRIT_OK;
+  };
+  if (fine) {
+    bd.nl = fine->nl;
+    bd.ncl = fine->ncl;
+    bd.nr = fine->nr;
+    bd.ncr = fine->ncr;
+    bd.nf = F ? fine->nf : 0;
+    if ((rc = put(fine->lblk, &bd.lblk)) || (rc = put(fine->rblk, &bd.rblk))) return rc;
+    if (bd.nf > 0 && (rc = put(*F, &bd.F))) return rc;
+  }
+  return upload(&d_bnd, &bd, sizeof bd);
+}
+
 int OpDesc::upload(void** d, const void* h, size_t b) {
   if (dev_alloc(d, b) != MGRIT_OK) return MGRIT_ENOMEM;
   bytes += b;
@@ -370,6 +413,10 @@ void OpDesc::release() {
   dev_free(d_taps);
   dev_free(d_off);
   dev_free(d_sdirk);
+  dev_free(d_bnd);
+  for (void* q : d_extra) dev_free(q);
+  d_extra.clear();
+  d_bnd = nullptr;
   dev_free(d_mu);
   dev_free(d_tw);
   d_mu = d_tw = nullptr;
@@ -397,6 +444,9 @@ std::string OpDesc::describe() const {
   }
   else if (kind == OP_GENERIC)
     snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
+  else if (kind == OP_BOUNDED)
+    snprintf(buf, sizeof buf, "bounded ntaps=%d NT=%d%s", ntaps, NL,
+             d_extra.empty() ? "" : " +boundary rows");
   else
     snprintf(buf, sizeof buf, "sdirk<K=%d> NL=%d", K, NL);
   return buf;
@@ -410,7 +460,7 @@ static RelaxArgs base_args(const Plan& P, const OpDesc& op) {
   std::memset(&a, 0, sizeof a);
   a.taps = op.d_taps;
   a.tap_off = op.d_off;
-  a.sdirk = op.d_sdirk;
+  a.opdata = op.d_sdirk ? op.d_sdirk : op.d_bnd;
   a.ntaps = op.ntaps;
   a.omin = op.omin;
   a.nx = P.nx;
@@ -923,14 +973,23 @@ int mgrit_psi_optimize_bound(int scheme, double cfl, int nx, int nt, int m, int 
 }
 
 
-int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
-                      int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
-                      int relax, int precision, void* hip_stream) {
+}  // extern "C"
+
+namespace mgr {
+
+// Plans of both problems: periodic (inflow == NULL) or with inflow/outflow
+// boundaries and the inflow data rows of mgrit_plan_create_inflow.
+static int plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
+                       int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
+                       int relax, int precision, void* hip_stream, const double* inflow,
+                       int n_derivs) {
   if (!out) return MGRIT_EINVAL;
   *out = nullptr;
   Tableau t;
   if (!get_tableau(scheme, t) || nx < 2 || nt < 1 || m < 2 || levels < 2 ||
       !(alpha > 0.0) || !(cfl > 0.0) || !psi)
+    return MGRIT_EINVAL;
+  if (inflow && (t.implicit || precision != MGRIT_FP64 || n_derivs < t.p + 1))
     return MGRIT_EINVAL;
   if (cycle != MGRIT_CYCLE_V && cycle != MGRIT_CYCLE_F) return MGRIT_EINVAL;
   if (relax != MGRIT_RELAX_FCF && relax != MGRIT_RELAX_F) return MGRIT_EINVAL;
@@ -955,6 +1014,7 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
   P->cycle_kind = cycle;
   P->relax_kind = relax;
   P->precision = precision;
+  P->inflow = inflow != nullptr;
   P->dx = 2.0 / nx;
   P->dt = cfl * P->dx / alpha;
   P->scale = std::sqrt(P->dx * P->dt);
@@ -972,7 +1032,33 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
       L.op.stream = L.seq.stream = P->stream;
       L.n = (int)n;
       L.nc = (l < levels - 1) ? (int)(n / m) : 0;
-      if (l == 0) {
+      if (inflow && l == 0) {
+        InflowOp fop;
+        rc = inflow_setup(t, cfl, alpha, nx, fop, err);
+        if (!rc) {
+          // forcing of the step from t_n: row n = B g^(0..p)(t_n)
+          std::vector<double> F((size_t)nt * fop.nf, 0.0);
+          for (long long r = 0; r < nt; ++r)
+            for (int i = 0; i < fop.nf; ++i) {
+              double v = 0.0;
+              for (int d = 0; d < fop.nd; ++d)
+                v += fop.B[(size_t)i * fop.nd + d] * inflow[r * n_derivs + d];
+              F[(size_t)r * fop.nf + i] = v;
+            }
+          rc = L.op.init_bounded(fop.interior, &fop, &F, nx, m, err);
+        }
+      } else if (inflow) {
+        // the periodic Psi truncated to the interval (signed offsets)
+        Taps f;
+        for (int i = 0; i < psi[l - 1].nnz; ++i) {
+          int o = ((psi[l - 1].offset[i] % nx) + nx) % nx;
+          if (o > nx / 2) o -= nx;
+          f.off.push_back(o);
+          f.w.push_back(psi[l - 1].weight[i]);
+        }
+        if (l < levels - 1) rc = L.op.init_bounded(f, nullptr, nullptr, nx, m, err);
+        else rc = L.seq.init_bounded(f, nullptr, nullptr, nx, m, err);
+      } else if (l == 0) {
         if (t.implicit) rc = L.op.init_sdirk(t, cfl, nx, err);
         else {
           Taps f;
@@ -1014,7 +1100,7 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
         !(P->h_norm = take_host_word()))
       return fail(MGRIT_ENOMEM);
     P->bytes += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);
-    if (spectral_supported(nx)) {
+    if (!inflow && spectral_supported(nx)) {
       // the coarsest stencil's eigenvalues and the transform's twiddles
       Level& C = P->lev.back();
       Taps f;
@@ -1053,6 +1139,51 @@ int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cf
     L.seq.staged.clear();
   }
   *out = reinterpret_cast<mgrit_plan_t>(P);
+  return MGRIT_OK;
+}
+
+}  // namespace mgr
+
+extern "C" {
+
+int mgrit_plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
+                      int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
+                      int relax, int precision, void* hip_stream) {
+  return plan_create(out, nx, nt, alpha, cfl, scheme, m, levels, psi, cycle, relax, precision,
+                     hip_stream, nullptr, 0);
+}
+
+int mgrit_plan_create_inflow(mgrit_plan_t* out, int nx, int nt, double alpha, double cfl,
+                             int scheme, int m, int levels, const mgrit_taps* psi, int cycle,
+                             int relax, const double* inflow, int n_derivs, void* hip_stream) {
+  if (!inflow) return MGRIT_EINVAL;
+  return plan_create(out, nx, nt, alpha, cfl, scheme, m, levels, psi, cycle, relax, MGRIT_FP64,
+                     hip_stream, inflow, n_derivs);
+}
+
+int mgrit_inflow_operator(int scheme, double cfl, double alpha, int nx, double* phi, double* B,
+                          int* n_derivs) {
+  Tableau t;
+  if (!get_tableau(scheme, t) || t.implicit || nx < 2 || !(cfl > 0.0) || !(alpha > 0.0) ||
+      !n_derivs)
+    return MGRIT_EINVAL;
+  InflowOp op;
+  std::string err;
+  int rc;
+  try {
+    rc = inflow_setup(t, cfl, alpha, nx, op, err);
+  } catch (...) {
+    return MGRIT_ENOMEM;
+  }
+  if (rc) return rc;
+  *n_derivs = op.nd;
+  if (phi)
+    for (int i = 0; i < nx; ++i)
+      for (int c = 0; c < nx; ++c) phi[(size_t)i * nx + c] = inflow_entry(op, nx, i, c);
+  if (B)
+    for (int i = 0; i < nx; ++i)
+      for (int d = 0; d < op.nd; ++d)
+        B[(size_t)i * op.nd + d] = i < op.nf ? op.B[(size_t)i * op.nd + d] : 0.0;
   return MGRIT_OK;
 }
 
@@ -1173,6 +1304,11 @@ int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
   a.nint = batch;
   a.out = out;
   a.out_off = 0;
+  if (op.kind == OP_BOUNDED) {
+    // every row steps from t = 0 with the plan's inflow data (n_t rows)
+    if (ksteps > P->nt) return MGRIT_EINVAL;
+    a.omin = 0;
+  }
   const int prec = P->precision == MGRIT_FP32_RELAX ? 1 : 0;
   return P->launch(op, prec, a, batch, MGRIT_PROF_RELAX_FINE);
 }

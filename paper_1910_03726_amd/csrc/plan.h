@@ -13,7 +13,7 @@
 
 namespace mgr {
 
-enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2 };
+enum OpKind { OP_STENCIL = 0, OP_GENERIC = 1, OP_SDIRK = 2, OP_BOUNDED = 3 };
 
 // Fine-level residual passes write one partial sum per interval and tile.
 constexpr int kMaxFineTiles = 16;
@@ -55,6 +55,8 @@ struct OpDesc {
   double* d_taps = nullptr;
   int* d_off = nullptr;
   void* d_sdirk = nullptr;
+  void* d_bnd = nullptr;                // bounded kernel: device BoundedDev
+  std::vector<void*> d_extra;           // bounded kernel: its blocks and forcing
   size_t bytes = 0;
   hipStream_t stream = nullptr;         // allocation and upload stream
   std::vector<std::vector<char>> staged;  // host sources of pending uploads
@@ -69,6 +71,12 @@ struct OpDesc {
   int init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, int max_tiles,
                    std::string& err);
   int init_sdirk(const Tableau& t, double cfl, int nx, std::string& err);
+  // inflow/outflow levels (Sec. 4.5): `interior` with signed offsets; the
+  // fine level also brings its boundary rows and the forcing table F
+  // (nt rows of fine->nf values); `stride`: fine steps between the start
+  // times of consecutive blocks of a pass
+  int init_bounded(const Taps& interior, const InflowOp* fine, const std::vector<double>* F,
+                   int nx, int stride, std::string& err);
   void release();
   std::string describe() const;
 };
@@ -114,6 +122,7 @@ struct ProfPending {
 struct Plan {
   int nx = 0, nt = 0, m = 0, scheme = 0;
   int cycle_kind = 0, relax_kind = 0, precision = 0;
+  bool inflow = false;  // inflow/outflow boundaries (Sec. 4.5)
   double alpha = 1.0, cfl = 0.0, dx = 0.0, dt = 0.0, scale = 0.0;
   hipStream_t stream = nullptr;
   std::vector<Level> lev;

@@ -31,6 +31,9 @@ struct KernelTable {
   BatchFn stencil_b[2][kNumK][kNumWidths][2] = {};
   BatchFn sdirk_b[2][kNumSdirkK][kNumSdirkShapes] = {};
   BatchFn generic_b[2] = {};
+  // inflow/outflow boundaries (bounded_kernels.h), FP64 state
+  KernelFn bounded = nullptr;
+  BatchFn bounded_b = nullptr;
 };
 
 // Filled once on first use; prec 0 = FP64 state, 1 = FP32 state.

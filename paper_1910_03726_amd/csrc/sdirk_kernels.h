@@ -159,7 +159,7 @@ __device__ __forceinline__ void sdirk_body(const RelaxArgs& a, const int j) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ T scan[2][32];
   __shared__ double red[16];
-  const SdirkDev* sd = reinterpret_cast<const SdirkDev*>(a.sdirk);
+  const SdirkDev* sd = reinterpret_cast<const SdirkDev*>(a.opdata);
   const int NL = blockDim.x, lane = threadIdx.x, nx = a.nx, m = a.m;
   const Stager<K> St{reinterpret_cast<double*>(smem_raw), nx, NL, lane};
 

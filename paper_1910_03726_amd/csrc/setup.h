@@ -80,6 +80,22 @@ int psi_hierarchy(int scheme, double cfl, int nx, int m, int levels, int rule,
 void tap_window(const Taps& t, int nx, int& omin, int& W,
                 std::vector<double>& dense);
 
+// Sec. 4.5: the step of ERKp+Up on (-1, 1] with inflow data at x = -1 as
+// u^{n+1} = Phi u^n + B gd_n, gd_n = g^(d)(t_n), d = 0..p (inflow_setup.cpp).
+struct InflowOp {
+  Taps interior;                 // Phi away from the ends, signed offsets
+  int nl = 0, ncl = 0;           // rows 0..nl-1 over columns 0..ncl-1
+  std::vector<double> lblk;      // nl x ncl, row-major
+  int nr = 0, ncr = 0;           // rows nx-nr.. over columns nx-ncr..
+  std::vector<double> rblk;      // nr x ncr
+  int nf = 0, nd = 0;            // forcing rows 0..nf-1: B is nf x nd
+  std::vector<double> B;
+};
+int inflow_setup(const Tableau& t, double cfl, double alpha, int nx, InflowOp& out,
+                 std::string& err);
+// Phi[i][c] as the bounded kernel applies it
+double inflow_entry(const InflowOp& op, int nx, int i, int c);
+
 // SDIRK: factor M = I - gamma dt L into cyclic recurrences (see common.h)
 // and fill the stage data; scan constants for chunk K and NL lanes.
 bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,

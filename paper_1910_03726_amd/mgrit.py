@@ -132,6 +132,11 @@ _SIGS = {
                                       ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mgrit_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _I, _I, _I,
                                ctypes.POINTER(Taps), _I, _I, _I, _P]),
+    "mgrit_plan_create_inflow": (_I, [ctypes.POINTER(_P), _I, _I, _D, _D, _I, _I, _I,
+                                      ctypes.POINTER(Taps), _I, _I, ctypes.POINTER(_D), _I,
+                                      _P]),
+    "mgrit_inflow_operator": (_I, [_I, _D, _D, _I, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                   ctypes.POINTER(_I)]),
     "mgrit_solve": (_I, [_P, _P, _P, _D, _I, _P, _I, ctypes.POINTER(_D),
                          ctypes.POINTER(_I)]),
     "mgrit_solve_batch": (_I, [_I, ctypes.POINTER(_P), ctypes.POINTER(_P),
@@ -265,6 +270,21 @@ def psi_optimize_bound(scheme, cfl, nx, nt, m, levels, target=1e-3):
     return out, list(bounds), mi.value
 
 
+def inflow_operator(scheme, cfl, nx, alpha=1.0):
+    """(Phi, B) of the inflow/outflow fine step (mgrit_inflow_operator):
+    u^{n+1} = Phi u^n + B (g^(d)(t_n))_d, dense, host only."""
+    nd = _I()
+    _check(lib().mgrit_inflow_operator(_scheme(scheme), cfl, alpha, nx, None, None,
+                                       ctypes.byref(nd)), "mgrit_inflow_operator")
+    phi = np.empty((nx, nx))
+    B = np.empty((nx, nd.value))
+    _check(lib().mgrit_inflow_operator(_scheme(scheme), cfl, alpha, nx,
+                                       phi.ctypes.data_as(ctypes.POINTER(_D)),
+                                       B.ctypes.data_as(ctypes.POINTER(_D)), ctypes.byref(nd)),
+           "mgrit_inflow_operator")
+    return phi, B
+
+
 def workload_psi(w):
     """The coarse operators of a workload description (inputs.WORKLOADS):
     (list of (offsets, weights), max_imag)."""
@@ -302,10 +322,14 @@ class SolveResult:
 
 
 class Plan:
-    """An MGRIT plan on the current HIP device (see mgrit_plan_create)."""
+    """An MGRIT plan on the current HIP device (see mgrit_plan_create).
+
+    ``inflow``: for the inflow/outflow problem (mgrit_plan_create_inflow),
+    an (n_t, >= p+1) array of the inflow data's derivatives g^(d)(n dt).
+    """
 
     def __init__(self, nx, nt, cfl, scheme, m, levels, psi, alpha=1.0, cycle="V",
-                 relax="FCF", precision="fp64", stream=None, coarse="auto"):
+                 relax="FCF", precision="fp64", stream=None, coarse="auto", inflow=None):
         import torch
         self.nx, self.nt, self.m, self.levels = int(nx), int(nt), int(m), int(levels)
         self.scheme = scheme
@@ -324,11 +348,23 @@ class Plan:
             arr[i].offset = oa
             arr[i].weight = wa
         h = _P()
-        rc = lib().mgrit_plan_create(ctypes.byref(h), self.nx, self.nt, alpha, cfl,
-                                     _scheme(scheme), self.m, self.levels, arr,
-                                     CYCLES[cycle], RELAX[relax], PRECISION[precision],
-                                     ctypes.c_void_p(stream))
-        _check(rc, "mgrit_plan_create")
+        if inflow is None:
+            rc = lib().mgrit_plan_create(ctypes.byref(h), self.nx, self.nt, alpha, cfl,
+                                         _scheme(scheme), self.m, self.levels, arr,
+                                         CYCLES[cycle], RELAX[relax], PRECISION[precision],
+                                         ctypes.c_void_p(stream))
+            _check(rc, "mgrit_plan_create")
+        else:
+            if precision != "fp64":
+                raise MgritError(EINVAL, "inflow plans are FP64")
+            g = np.ascontiguousarray(inflow, dtype=np.float64)
+            if g.ndim != 2 or g.shape[0] != self.nt:
+                raise ValueError("inflow must be an (n_t, n_derivs) array")
+            rc = lib().mgrit_plan_create_inflow(
+                ctypes.byref(h), self.nx, self.nt, alpha, cfl, _scheme(scheme), self.m,
+                self.levels, arr, CYCLES[cycle], RELAX[relax],
+                g.ctypes.data_as(ctypes.POINTER(_D)), g.shape[1], ctypes.c_void_p(stream))
+            _check(rc, "mgrit_plan_create_inflow")
         self._h = h
         if coarse != "auto":
             self.set_coarse_solver(coarse)

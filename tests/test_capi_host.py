@@ -10,7 +10,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle import coarse, rk
+from oracle import coarse, rk, inflow
 from paper_1910_03726_amd import mgrit as M
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -125,6 +125,28 @@ def test_psi_optimize_bound_matches_oracle(scheme, nx, nt, m, L, target):
 def test_psi_optimize_bound_rejects_sdirk():
     with pytest.raises(M.MgritError):
         M.psi_optimize_bound("SDIRK3", 4.0, 256, 1024, 4, 2)
+
+
+@pytest.mark.parametrize("scheme,nx,alpha", [("ERK1", 16, 1.0), ("ERK2", 40, 0.7),
+                                             ("ERK3", 64, 1.0), ("ERK4", 200, 1.3),
+                                             ("ERK5", 200, 1.0), ("ERK5", 700, 1.0),
+                                             ("ERK3", 1000, 2.0)])
+def test_inflow_operator_matches_oracle(scheme, nx, alpha):
+    # Phi as the bounded kernel applies it (dense corner blocks + the
+    # truncated periodic stencil) and the forcing matrix B, against the
+    # oracle's staged step applied to unit vectors and unit data
+    c = rk.paper_cfl(scheme)
+    d = inflow.InflowDiscretization(scheme, nx, c, alpha=alpha)
+    phi, B = M.inflow_operator(scheme, c, nx, alpha)
+    assert np.max(np.abs(phi - d.dense_phi())) <= 4e-15
+    nd = d.n_derivs()
+    Bo = np.stack([d.forcing(np.eye(nd)[k]) for k in range(nd)], axis=1)
+    assert np.max(np.abs(B - Bo)) <= 1e-14 * np.max(np.abs(Bo))
+
+
+def test_inflow_operator_rejects_sdirk():
+    with pytest.raises(M.MgritError):
+        M.inflow_operator("SDIRK3", 4.0, 64)
 
 
 def test_psi_redisc_is_erk_at_m_times_c():
