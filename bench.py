@@ -42,9 +42,11 @@ TOL = 1e-10
 
 def _plan(w, precision=None):
     from paper_1910_03726_amd import mgrit as M
+    from paper_1910_03726_amd import inputs
     psi, mi = M.workload_psi(w)
+    inflow = inputs.workload_inflow(w) if w.get("boundary") == "inflow" else None
     P = M.Plan(w["nx"], w["nt"], w["cfl"], w["scheme"], w["m"], w["levels"], psi,
-               cycle=w["cycle"], precision=precision or w["precision"])
+               cycle=w["cycle"], precision=precision or w["precision"], inflow=inflow)
     return P, psi
 
 

@@ -360,21 +360,58 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
                          const std::vector<double>* F, int nx, int stride, std::string& err) {
   const KernelTable& kt = kernel_table();
   kind = OP_BOUNDED;
-  NL = 256;
-  fn[0] = kt.bounded;
-  bfn[0] = kt.bounded_b;
   fn[1] = nullptr;  // FP64 state only
   bfn[1] = nullptr;
-  shmem[0] = shmem[1] = (size_t)2 * nx * sizeof(double);
+  nnz = (int)interior.off.size();
+  omin = stride;
+  // register-blocked kernel: the taps as one dense window of a compiled
+  // width, chunks of kBoundedK points
+  int omx = -(1 << 30), omn = 1 << 30;
+  for (int o : interior.off) {
+    omx = std::max(omx, o);
+    omn = std::min(omn, o);
+  }
+  const int W = nnz ? omx - omn + 1 : 1;
+  int wi = -1;
+  for (int i = 0; i < kNumBoundedWidths && wi < 0; ++i)
+    if (kBoundedWidths[i] >= W) wi = i;
+  const int nch = (nx + kBoundedK - 1) / kBoundedK;
+  int rc;
+  // (one thread per boundary row, the rows staged in LDS after the state)
+  const int nbrows = fine ? fine->nl + fine->nr : 0;
+  const size_t tiled_lds =
+      sizeof(double) * ((size_t)2 * nx + (fine ? (size_t)fine->nl * fine->ncl +
+                                                     (size_t)fine->nr * fine->ncr
+                                               : 0));
+  if (nnz && wi >= 0 && kt.bounded_tiled[wi] && nbrows <= 512 &&
+      tiled_lds <= kernel_info(kt.bounded_tiled[wi]).max_lds) {
+    const int Wb = kBoundedWidths[wi];
+    std::vector<double> dense(Wb, 0.0);
+    for (size_t t = 0; t < interior.off.size(); ++t) dense[omx - interior.off[t]] += interior.w[t];
+    const int one = omx;
+    fn[0] = kt.bounded_tiled[wi];
+    bfn[0] = kt.bounded_tiled_b[wi];
+    NL = std::min(512, (std::max(nch, nbrows) + 63) / 64 * 64);
+    shmem[0] = shmem[1] = tiled_lds;
+    ntaps = Wb;
+    width = W;
+    Wbucket = Wb;
+    rc = upload((void**)&d_taps, dense.data(), dense.size() * sizeof(double));
+    if (!rc) rc = upload((void**)&d_off, &one, sizeof(int));
+  } else {
+    fn[0] = kt.bounded;
+    bfn[0] = kt.bounded_b;
+    NL = 256;
+    shmem[0] = shmem[1] = (size_t)2 * nx * sizeof(double);
+    ntaps = nnz;
+    Wbucket = 0;
+    rc = upload((void**)&d_taps, interior.w.data(), interior.w.size() * sizeof(double));
+    if (!rc) rc = upload((void**)&d_off, interior.off.data(), interior.off.size() * sizeof(int));
+  }
   if (!fn[0] || shmem[0] > kernel_info(fn[0]).max_lds) {
     err = "n_x too large for the bounded relaxation kernel";
     return MGRIT_EINVAL;
   }
-  nnz = (int)interior.off.size();
-  ntaps = nnz;
-  omin = stride;
-  int rc = upload((void**)&d_taps, interior.w.data(), interior.w.size() * sizeof(double));
-  if (!rc) rc = upload((void**)&d_off, interior.off.data(), interior.off.size() * sizeof(int));
   if (rc) return rc;
   BoundedDev bd;
   std::memset(&bd, 0, sizeof bd);
@@ -445,8 +482,12 @@ std::string OpDesc::describe() const {
   else if (kind == OP_GENERIC)
     snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
   else if (kind == OP_BOUNDED)
-    snprintf(buf, sizeof buf, "bounded ntaps=%d NT=%d%s", ntaps, NL,
+  {
+    char kw[32] = "";
+    if (Wbucket) snprintf(kw, sizeof kw, "<K=%d,W=%d>", kBoundedK, Wbucket);
+    snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s", kw, ntaps, NL,
              d_extra.empty() ? "" : " +boundary rows");
+  }
   else
     snprintf(buf, sizeof buf, "sdirk<K=%d> NL=%d", K, NL);
   return buf;

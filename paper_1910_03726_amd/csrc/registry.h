@@ -31,10 +31,17 @@ struct KernelTable {
   BatchFn stencil_b[2][kNumK][kNumWidths][2] = {};
   BatchFn sdirk_b[2][kNumSdirkK][kNumSdirkShapes] = {};
   BatchFn generic_b[2] = {};
-  // inflow/outflow boundaries (bounded_kernels.h), FP64 state
+  // inflow/outflow boundaries (bounded_kernels.h), FP64 state: point by
+  // point, and register-blocked (K = kBoundedK points per thread) for the
+  // window widths kBoundedWidths
   KernelFn bounded = nullptr;
   BatchFn bounded_b = nullptr;
+  KernelFn bounded_tiled[8] = {};
+  BatchFn bounded_tiled_b[8] = {};
 };
+constexpr int kBoundedK = 9;  // odd: lanes K doubles apart hit distinct LDS banks
+constexpr int kNumBoundedWidths = 8;
+constexpr int kBoundedWidths[kNumBoundedWidths] = {4, 8, 12, 16, 24, 32, 48, 64};
 
 // Filled once on first use; prec 0 = FP64 state, 1 = FP32 state.
 const KernelTable& kernel_table();

@@ -115,12 +115,27 @@ WORKLOADS = {
         scheme="ERK5", nx=8192, nt=65536, cfl=erk_cfl(5), m=8, levels=5,
         cycle="V", precision="fp32", psi_rule="bound", psi_widths=None, psi_target=1e-3,
         u0=dict(nmodes=16, decay=0.0, seed=0), init_seed=1),
+    # inflow/outflow boundaries (Sec. 4.5): u(-1, t) = sin^4(pi t), u0 the
+    # exact solution's initial profile, the periodic Psi truncated
+    "erk3_u3_inflow_nx4096_nt16384_m8_vcycle": dict(
+        scheme="ERK3", nx=4096, nt=16384, cfl=erk_cfl(3), m=8, levels=4,
+        cycle="V", precision="fp64", psi_rule="window", psi_widths=None,
+        boundary="inflow", init_seed=1),
 }
 
 
 def workload_u0(w):
+    if w.get("boundary") == "inflow":
+        return np.sin(np.pi * (inflow_grid(w["nx"]) + 1.0)) ** 4
     return fourier_u0(w["nx"], w["u0"]["nmodes"], w["u0"]["seed"],
                       w["u0"]["decay"])
+
+
+def workload_inflow(w, alpha=1.0):
+    """Inflow data rows of an inflow workload (sin^4(pi t), derivatives 0..p)."""
+    p = int(w["scheme"][-1])
+    dt = w["cfl"] * (2.0 / w["nx"]) / alpha
+    return sin4_inflow_derivs(w["nt"], dt, p + 1)
 
 
 def serving_requests(n, seed=7, nx_exps=range(8, 14), nt_exps=range(10, 16),
