@@ -2,16 +2,18 @@
 //
 // Phi is no longer circulant: rows near x = -1 and x = 1 carry the boundary
 // closures, the coarse operators are the periodic Psi truncated to the
-// interval, and every fine step adds the inflow forcing of its time.  The
-// kernel keeps one interval's state in LDS (two n_x buffers, FP64) and
-// applies the operator of BoundedDev (common.h) point by point: consecutive
-// threads own consecutive points, so tap reads from LDS are conflict-free.
+// interval, and every fine step adds the inflow forcing of its time.  Both
+// kernels keep one interval's state in LDS (FP64) and apply the operator of
+// BoundedDev (common.h): k_bounded point by point (any tap list; consecutive
+// threads own consecutive points), k_bounded_tiled register-blocked over a
+// dense window of up to 64 taps (below).
 // Launch arguments and outputs are those of the periodic kernels
 // (RelaxArgs, relax_kernels.h), with `opdata` the level's BoundedDev,
 // signed offsets in `tap_off` and `omin` the fine steps between the start
 // times of consecutive blocks.
 #pragma once
 
+#include "registry.h"
 #include "relax_kernels.h"
 
 namespace mgr {
@@ -108,18 +110,34 @@ __device__ __forceinline__ void bounded_body(const RelaxArgs& a, const int j) {
   }
 }
 
+constexpr int kFRows = kFRowsLds;
+
+// Barrier for LDS traffic only: release and acquire at workgroup scope on
+// the local address space, so global loads issued for a later step stay in
+// flight across it (a full __syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Register-blocked variant.  Thread t owns chunks of K consecutive points;
 // the truncated stencil is a dense window of W weights, c[i] the weight of
 // offset omax - i (tap_off[0] = omax, taps = the W weights), so
 // out_{b+k} = sum_i c[i] u_{b - omax + k + i} with u = 0 off the grid (the
 // truncation).  A chunk reads its K + W - 1 inputs from LDS once into
-// registers (zero where the window leaves the grid).  K is odd, so lanes
+// registers; the state buffers carry padl / padr zero points on either side
+// (BoundedDev), so those reads need no bounds checks.  K is odd, so lanes
 // whose chunks start K doubles apart read distinct LDS banks.  The dense
 // boundary rows of the fine level are staged in LDS at the start and
-// computed one row per thread.  Right-hand side rows and the inflow
-// forcing are loaded before the arithmetic that precedes their use.
-// LDS: state and next state (2 n_x), then the left and right blocks.
-template <int K, int W>
+// computed one row per thread.  The inflow forcing is staged in LDS for
+// kFRows steps at a time; with PF (levels with a right-hand side every
+// step) the right-hand side rows of a thread's first chunk are loaded at
+// the end of the step before their use.  Steps are separated by LDS-only
+// barriers, so those loads stay in flight across them.
+// LDS: state and next state (each padl + n_x + padr), the left and right
+// blocks, then kFRows forcing rows.
+template <int K, int W, bool PF>
 __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int j) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
@@ -127,21 +145,43 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
   const int nx = a.nx, m = a.m, NT = blockDim.x, tid = threadIdx.x;
   const int omax = a.tap_off[0];
   const int nch = (nx + K - 1) / K;
-  double* cur = reinterpret_cast<double*>(smem_raw);
-  double* nxt = cur + nx;
-  double* lb = nxt + nx;
-  double* rb = lb + bd.nl * bd.ncl;
-  for (int q = tid; q < bd.nl * bd.ncl; q += NT) lb[q] = bd.lblk[q];
-  for (int q = tid; q < bd.nr * bd.ncr; q += NT) rb[q] = bd.rblk[q];
-  for (int p = tid; p < nx; p += NT) {
-    double v = 0.0;
-    if (!a.zero_in) {
-      v = a.in[(long long)j * a.in_stride * nx + p];
-      if (a.corr) v += a.corr[(long long)j * a.corr_stride * nx + p];
+  const int span = bd.padl + nx + bd.padr;
+  double* bufa = reinterpret_cast<double*>(smem_raw);
+  double* cur = bufa + bd.padl;
+  double* nxt = bufa + span + bd.padl;
+  // boundary rows staged with odd row strides (distinct LDS banks per row)
+  const int lst = bd.ncl | 1, rst = bd.ncr | 1;
+  double* lb = bufa + 2 * span;
+  double* rb = lb + bd.nl * lst;
+  for (int q = tid; q < bd.padl; q += NT) bufa[q] = bufa[span + q] = 0.0;
+  for (int q = tid; q < bd.padr; q += NT) cur[nx + q] = nxt[nx + q] = 0.0;
+  for (int q = tid; q < bd.nl * bd.ncl; q += NT) lb[(q / bd.ncl) * lst + q % bd.ncl] = bd.lblk[q];
+  for (int q = tid; q < bd.nr * bd.ncr; q += NT) rb[(q / bd.ncr) * rst + q % bd.ncr] = bd.rblk[q];
+  // start state: loads issued in batches of BL per thread before their use
+  constexpr int BL = 8;
+  {
+    const double* in = a.zero_in ? nullptr : a.in + (long long)j * a.in_stride * nx;
+    const double* co = (a.zero_in || !a.corr) ? nullptr : a.corr + (long long)j * a.corr_stride * nx;
+    double* o0 = a.mode == MODE_F ? a.out + (long long)j * m * nx
+                                  : ((a.mode == MODE_FC && a.write_row0 && j == 0) ? a.out : nullptr);
+    for (int p0 = tid; p0 < nx; p0 += BL * NT) {
+      double v[BL], c2[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        v[u] = (in && p < nx) ? in[p] : 0.0;
+        c2[u] = (co && p < nx) ? co[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        if (p < nx) {
+          const double x = v[u] + c2[u];
+          if (o0) o0[p] = x;
+          cur[p] = x;
+        }
+      }
     }
-    if (a.mode == MODE_F) a.out[(long long)j * m * nx + p] = v;
-    else if (a.mode == MODE_FC && a.write_row0 && j == 0) a.out[p] = v;
-    cur[p] = v;
   }
   if (a.mode == MODE_F && j == a.nint) return;
   __syncthreads();
@@ -153,19 +193,29 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
   }
   // boundary row of this thread (fine level), or -1
   const int brow = tid < bd.nl ? tid : (tid < bd.nl + bd.nr ? nx - bd.nr + (tid - bd.nl) : -1);
+  // inflow forcing rows, staged in LDS kFRows steps at a time
+  double* fst = rb + bd.nr * rst;
   const double* Fb = bd.F ? bd.F + (long long)j * a.omin * bd.nf : nullptr;
-  double fnext = (Fb && brow >= 0 && brow < bd.nf && m >= 1) ? Fb[brow] : 0.0;
+  const bool has_g = a.rhs_mode == RHS_EVERY;
+  const int b0 = tid * K;  // the thread's first chunk
+  constexpr int KP = PF ? K : 1;
+  double gnext[KP];
+  if (PF && has_g) {
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      gnext[k] = (m >= 1 && b0 + k < nx) ? a.rhs[((long long)j * m + 1) * nx + b0 + k] : 0.0;
+  }
   for (int s = 1; s <= m; ++s) {
-    const double* g = (a.rhs_mode == RHS_EVERY) ? a.rhs + ((long long)j * m + s) * nx : nullptr;
+    const double* g = has_g ? a.rhs + ((long long)j * m + s) * nx : nullptr;
     const bool store = a.mode == MODE_F && (s < m || a.write_last);
     double* orow = store ? a.out + ((long long)j * m + s) * nx : nullptr;
-    const double fcur = fnext;
-    if (Fb && brow >= 0 && brow < bd.nf && s < m) fnext = Fb[(long long)s * bd.nf + brow];
+    if (Fb && (s - 1) % kFRows == 0) {
+      const int rows = min(kFRows, m - (s - 1));
+      for (int q = tid; q < rows * bd.nf; q += NT) fst[q] = Fb[(long long)(s - 1) * bd.nf + q];
+      __syncthreads();
+    }
     for (int ch = tid; ch < nch; ch += NT) {
       const int b = ch * K;
-      double gv[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) gv[k] = (g && b + k < nx) ? g[b + k] : 0.0;
       // stream the K + W - 1 window values: value i feeds out_k with
       // weight c[i - k]
       double acc[K];
@@ -174,58 +224,85 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
       const int w0 = b - omax;
 #pragma unroll
       for (int i = 0; i < K + W - 1; ++i) {
-        const int q = w0 + i;
-        const double v = (unsigned)q < (unsigned)nx ? cur[q] : 0.0;
+        const double v = cur[w0 + i];
 #pragma unroll
         for (int k = 0; k < K; ++k)
           if (i - k >= 0 && i - k < W)
             acc[k] = fma(kHold ? c[kHold ? i - k : 0] : a.taps[i - k], v, acc[k]);
       }
+      if (has_g) {  // uniform
+        if (PF && ch == tid) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc[k] += gnext[PF ? k : 0];
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc[k] += b + k < nx ? g[b + k] : 0.0;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int p = b + k;
         if (p < nx && p >= bd.nl && p < nx - bd.nr) {
-          const double o = acc[k] + gv[k];
-          nxt[p] = o;
-          if (orow) orow[p] = o;
+          nxt[p] = acc[k];
+          if (orow) orow[p] = acc[k];
         }
       }
     }
     if (brow >= 0) {
       double acc = 0.0;
       if (brow < bd.nl) {
-        const double* row = lb + brow * bd.ncl;
+        const double* row = lb + brow * lst;
 #pragma unroll 4
         for (int q = 0; q < bd.ncl; ++q) acc = fma(row[q], cur[q], acc);
       } else {
-        const double* row = rb + (brow - (nx - bd.nr)) * bd.ncr;
+        const double* row = rb + (brow - (nx - bd.nr)) * rst;
         const double* src = cur + (nx - bd.ncr);
 #pragma unroll 4
         for (int q = 0; q < bd.ncr; ++q) acc = fma(row[q], src[q], acc);
       }
-      if (brow < bd.nf) acc += fcur;
-      if (g) acc += g[brow];
+      if (Fb && brow < bd.nf) acc += fst[((s - 1) % kFRows) * bd.nf + brow];
+      if (has_g) acc += g[brow];
       nxt[brow] = acc;
       if (orow) orow[brow] = acc;
     }
-    __syncthreads();
+    // next step's right-hand side for the first chunk, in flight across
+    // the barrier
+    if (PF && has_g && s < m) {
+#pragma unroll
+      for (int k = 0; k < KP; ++k) gnext[k] = b0 + k < nx ? g[nx + b0 + k] : 0.0;
+    }
+    lds_barrier();
     double* tmp = cur;
     cur = nxt;
     nxt = tmp;
   }
   if (a.mode == MODE_FC) {
     const double* gc = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;
+    const double* in1 = (a.delta && !a.zero_in) ? a.in + (long long)(j + 1) * a.in_stride * nx : nullptr;
+    const double* co1 = (a.delta && a.corr) ? a.corr + (long long)(j + 1) * a.corr_stride * nx : nullptr;
+    double* orow = a.out + (long long)(j + a.out_off) * nx;
     double ss = 0.0;
-    for (int p = tid; p < nx; p += NT) {
-      double v = cur[p];
-      if (gc) v += gc[p];
-      a.out[(long long)(j + a.out_off) * nx + p] = v;
-      ss += v * v;
-      if (a.delta) {
-        double u = a.zero_in ? 0.0 : a.in[(long long)(j + 1) * a.in_stride * nx + p];
-        if (a.corr) u += a.corr[(long long)(j + 1) * a.corr_stride * nx + p];
-        a.delta[(long long)(j + 1) * nx + p] = v - u;
-        if (j == 0) a.delta[p] = 0.0;
+    for (int p0 = tid; p0 < nx; p0 += BL * NT) {
+      double gv[BL], iv[BL], cv[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        gv[u] = (gc && p < nx) ? gc[p] : 0.0;
+        iv[u] = (in1 && p < nx) ? in1[p] : 0.0;
+        cv[u] = (co1 && p < nx) ? co1[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        if (p < nx) {
+          const double v = cur[p] + gv[u];
+          orow[p] = v;
+          ss += v * v;
+          if (a.delta) {
+            a.delta[(long long)(j + 1) * nx + p] = v - (iv[u] + cv[u]);
+            if (j == 0) a.delta[p] = 0.0;
+          }
+        }
       }
     }
     if (a.partial) {
@@ -234,14 +311,26 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
     }
   } else if (a.mode == MODE_RES) {
     const double* gc = (a.rhs_mode == RHS_CPOINT) ? a.rhs + (long long)(j + 1) * nx : nullptr;
+    const double* ref = a.ref + (long long)(j + 1) * nx;
     double ss = 0.0;
-    for (int p = tid; p < nx; p += NT) {
-      double v = cur[p];
-      if (gc) v += gc[p];
-      v -= a.ref[(long long)(j + 1) * nx + p];
-      a.out[(long long)(j + 1) * nx + p] = v;
-      if (j == 0) a.out[p] = 0.0;
-      ss += v * v;
+    for (int p0 = tid; p0 < nx; p0 += BL * NT) {
+      double gv[BL], rv[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        gv[u] = (gc && p < nx) ? gc[p] : 0.0;
+        rv[u] = p < nx ? ref[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        if (p < nx) {
+          const double v = cur[p] + gv[u] - rv[u];
+          a.out[(long long)(j + 1) * nx + p] = v;
+          if (j == 0) a.out[p] = 0.0;
+          ss += v * v;
+        }
+      }
     }
     if (a.partial) {
       const double s = block_sum(ss, red);
@@ -258,16 +347,16 @@ __global__ void __launch_bounds__(256) k_bounded_b(BatchArgs b) {
   bounded_body(a, blk);
 }
 
-template <int K, int W>
+template <int K, int W, bool PF>
 __global__ void __launch_bounds__(512) k_bounded_tiled(RelaxArgs a) {
-  bounded_tiled_body<K, W>(a, (int)blockIdx.x);
+  bounded_tiled_body<K, W, PF>(a, (int)blockIdx.x);
 }
 
-template <int K, int W>
+template <int K, int W, bool PF>
 __global__ void __launch_bounds__(512) k_bounded_tiled_b(BatchArgs b) {
   int blk;
   const RelaxArgs a = batch_member(b, blk);
-  bounded_tiled_body<K, W>(a, blk);
+  bounded_tiled_body<K, W, PF>(a, blk);
 }
 
 }  // namespace mgr

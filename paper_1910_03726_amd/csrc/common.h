@@ -85,7 +85,11 @@ struct BatchArgs {
 // plus, on the fine level, the inflow forcing of the step from t_n:
 // F[n*nf + i] added to rows i < nf (F: one row per fine step).
 struct BoundedDev {
-  int nl, ncl, nr, ncr, nf, pad_;
+  int nl, ncl, nr, ncr, nf;
+  int padl, padr;  // register-blocked kernel: zero points kept in LDS left
+                   // and right of the state, so every window read is in
+                   // bounds and reads 0 off the grid (the truncation)
+  int pad_;
   const double* lblk;
   const double* rblk;
   const double* F;

@@ -6,8 +6,10 @@ namespace mgr {
 template <int W>
 static void reg_tiled(KernelTable& t, int i) {
   static_assert(W > 0, "");
-  t.bounded_tiled[i] = &k_bounded_tiled<kBoundedK, W>;
-  t.bounded_tiled_b[i] = &k_bounded_tiled_b<kBoundedK, W>;
+  t.bounded_tiled[0][i] = &k_bounded_tiled<bounded_k(W), W, false>;
+  t.bounded_tiled_b[0][i] = &k_bounded_tiled_b<bounded_k(W), W, false>;
+  t.bounded_tiled[1][i] = &k_bounded_tiled<bounded_k(W), W, true>;
+  t.bounded_tiled_b[1][i] = &k_bounded_tiled_b<bounded_k(W), W, true>;
 }
 
 void register_bounded(KernelTable& t) {

@@ -365,7 +365,7 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
   nnz = (int)interior.off.size();
   omin = stride;
   // register-blocked kernel: the taps as one dense window of a compiled
-  // width, chunks of kBoundedK points
+  // width, chunks of bounded_k(width) points
   int omx = -(1 << 30), omn = 1 << 30;
   for (int o : interior.off) {
     omx = std::max(omx, o);
@@ -375,22 +375,29 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
   int wi = -1;
   for (int i = 0; i < kNumBoundedWidths && wi < 0; ++i)
     if (kBoundedWidths[i] >= W) wi = i;
-  const int nch = (nx + kBoundedK - 1) / kBoundedK;
+  const int kb = wi >= 0 ? bounded_k(kBoundedWidths[wi]) : 1;
+  const int nch = (nx + kb - 1) / kb;
   int rc;
-  // (one thread per boundary row, the rows staged in LDS after the state)
+  // (one thread per boundary row, the rows staged in LDS after the state;
+  // zero padding around the state covers every window read)
   const int nbrows = fine ? fine->nl + fine->nr : 0;
+  const int Wt = wi >= 0 ? kBoundedWidths[wi] : 0;
+  const int padl = std::max(0, omx), padr = std::max(0, Wt - 1 - omx) + kb;
   const size_t tiled_lds =
-      sizeof(double) * ((size_t)2 * nx + (fine ? (size_t)fine->nl * fine->ncl +
-                                                     (size_t)fine->nr * fine->ncr
-                                               : 0));
-  if (nnz && wi >= 0 && kt.bounded_tiled[wi] && nbrows <= 512 &&
-      tiled_lds <= kernel_info(kt.bounded_tiled[wi]).max_lds) {
+      sizeof(double) * ((size_t)2 * (padl + nx + padr) +
+                        (fine ? (size_t)fine->nl * (fine->ncl | 1) +
+                                    (size_t)fine->nr * (fine->ncr | 1) +
+                                    (size_t)kFRowsLds * fine->nf
+                              : 0));
+  const int pf = fine ? 0 : 1;  // coarse levels add a right-hand side row every step
+  if (nnz && wi >= 0 && kt.bounded_tiled[pf][wi] && nbrows <= 512 &&
+      tiled_lds <= kernel_info(kt.bounded_tiled[pf][wi]).max_lds) {
     const int Wb = kBoundedWidths[wi];
     std::vector<double> dense(Wb, 0.0);
     for (size_t t = 0; t < interior.off.size(); ++t) dense[omx - interior.off[t]] += interior.w[t];
     const int one = omx;
-    fn[0] = kt.bounded_tiled[wi];
-    bfn[0] = kt.bounded_tiled_b[wi];
+    fn[0] = kt.bounded_tiled[pf][wi];
+    bfn[0] = kt.bounded_tiled_b[pf][wi];
     NL = std::min(512, (std::max(nch, nbrows) + 63) / 64 * 64);
     shmem[0] = shmem[1] = tiled_lds;
     ntaps = Wb;
@@ -415,6 +422,10 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
   if (rc) return rc;
   BoundedDev bd;
   std::memset(&bd, 0, sizeof bd);
+  if (Wbucket) {
+    bd.padl = padl;
+    bd.padr = padr;
+  }
   auto put = [&](const std::vector<double>& h, const double** dst) {
     if (h.empty()) return (int)MGRIT_OK;  // an empty block stays NULL
     void* d = nullptr;
@@ -484,7 +495,7 @@ std::string OpDesc::describe() const {
   else if (kind == OP_BOUNDED)
   {
     char kw[32] = "";
-    if (Wbucket) snprintf(kw, sizeof kw, "<K=%d,W=%d>", kBoundedK, Wbucket);
+    if (Wbucket) snprintf(kw, sizeof kw, "<K=%d,W=%d>", bounded_k(Wbucket), Wbucket);
     snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s", kw, ntaps, NL,
              d_extra.empty() ? "" : " +boundary rows");
   }

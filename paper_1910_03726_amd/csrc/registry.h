@@ -32,14 +32,19 @@ struct KernelTable {
   BatchFn sdirk_b[2][kNumSdirkK][kNumSdirkShapes] = {};
   BatchFn generic_b[2] = {};
   // inflow/outflow boundaries (bounded_kernels.h), FP64 state: point by
-  // point, and register-blocked (K = kBoundedK points per thread) for the
+  // point, and register-blocked (K = bounded_k(W) points per thread) for the
   // window widths kBoundedWidths
   KernelFn bounded = nullptr;
   BatchFn bounded_b = nullptr;
-  KernelFn bounded_tiled[8] = {};
-  BatchFn bounded_tiled_b[8] = {};
+  // [right-hand side rows prefetched (coarse levels)][width]
+  KernelFn bounded_tiled[2][8] = {};
+  BatchFn bounded_tiled_b[2][8] = {};
 };
-constexpr int kBoundedK = 9;  // odd: lanes K doubles apart hit distinct LDS banks
+// points per thread chunk by window width: odd, so lanes K doubles apart hit
+// distinct LDS banks; fewer for wide windows (register pressure)
+constexpr int bounded_k(int W) { return W >= 32 ? 5 : 9; }
+// inflow forcing rows the register-blocked kernel stages in LDS at a time
+constexpr int kFRowsLds = 64;
 constexpr int kNumBoundedWidths = 8;
 constexpr int kBoundedWidths[kNumBoundedWidths] = {4, 8, 12, 16, 24, 32, 48, 64};
 

@@ -162,3 +162,37 @@ def test_inflow_plan_limits():
     with M.Plan(128, 512, c, "ERK3", 4, 2, psi, inflow=G) as P:
         with pytest.raises(M.MgritError):
             P.set_coarse_solver("spectral")  # Psi is not circulant
+
+
+def test_wide_window_uses_the_point_kernel():
+    # a coarse operator spanning more than 64 points runs on the point-by-
+    # point kernel; results as the oracle's
+    s, nx, nt, m = "ERK1", 256, 256, 4
+    d, c, H, psi, G = _setup(s, nx, nt, m, 2, [3])
+    offs = np.array([0, 1, 2, 40, 79])
+    w = np.array([0.2, 0.5, 0.25, 0.03, 0.02])
+    H = [{"offsets": offs, "weights": w}]
+    u0 = np.sin(np.pi * (d.x + 1.0)) ** 4
+    uinit = inputs.random_iterate(nt // m + 1, nx, 2)
+    ref = _oracle(d, H, G, m, nt, u0, uinit, 1e-11, 80)
+    with M.Plan(nx, nt, c, s, m, 2, [(offs, w)], inflow=G) as P:
+        assert "L2 n=64: bounded ntaps=5" in P.describe()
+        r = P.solve(torch.tensor(u0, device="cuda"), torch.tensor(uinit, device="cuda"),
+                    tol=1e-11, maxit=80, out="cpoints")
+    assert r.iters == ref.iters
+    for a, b in zip(r.hist, ref.hist):
+        assert abs(a - b) <= 1e-9 * ref.hist[0] + 1e-6 * b
+
+
+def test_several_chunks_per_thread():
+    # n_x = 8192: more chunks than threads in the register-blocked kernel
+    s, nx, nt, m, L = "ERK3", 8192, 512, 4, 3
+    d, c, H, psi, G = _setup(s, nx, nt, m, L)
+    u0 = np.sin(np.pi * (d.x + 1.0)) ** 4
+    with M.Plan(nx, nt, c, s, m, L, psi, inflow=G) as P:
+        assert "bounded<K=9" in P.describe()
+        r = P.solve(torch.tensor(u0, device="cuda"), None, tol=1e-12, maxit=60, out="final")
+    assert r.status == M.OK
+    ref = d.time_stepping(u0, G, every=nt)[-1]
+    assert np.max(np.abs(r.out.cpu().numpy()[0] - ref)) <= 1e-10
+
