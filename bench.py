@@ -87,19 +87,19 @@ def _fine_nnz(w):
     return len(off)
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, source="relax_kernels.h"):
     """HBM bytes per launch of the fine relaxation kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
     changed since the counters were taken (hash recorded in the summary)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")
-    src = os.path.join(ROOT, "paper_1910_03726_amd", "csrc", "relax_kernels.h")
+    src = os.path.join(ROOT, "paper_1910_03726_amd", "csrc", source)
     if not os.path.exists(path):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     rec, val = None, None
     for line in open(path):
-        if line.startswith("kernel source (relax_kernels.h) sha256[:16]:"):
+        if line.startswith(f"kernel source ({source}) sha256[:16]:"):
             rec = line.rsplit(":", 1)[1].strip()
         if line.startswith("traffic_bytes_per_launch:"):
             val = float(line.split(":", 1)[1])
@@ -113,6 +113,7 @@ def roofline(P, w, u0, uinit, torch, workload):
     prof = P.profile()
     P.set_profiling(False)
     nx, m = w["nx"], w["m"]
+    inflow = w.get("boundary") == "inflow"
     nc = w["nt"] // m
     it = r.iters
     # FC passes read the start C-point (and the correction after the first
@@ -131,8 +132,10 @@ def roofline(P, w, u0, uinit, torch, workload):
     out = {"bound": "hbm" if t_hbm >= t_alu else "alu",
            "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-           "traffic": measured_traffic(workload),
-           "kernel": "k_stencil (fine-level FC and residual passes)",
+           "traffic": measured_traffic(workload, "bounded_kernels.h" if inflow else
+                                       "relax_kernels.h"),
+           "kernel": ("k_bounded_tiled" if inflow else "k_stencil") +
+                     " (fine-level FC and residual passes)",
            "launches": launches, "avg_launch_ms": round(avg_ms, 5),
            "bytes_per_launch": bytes_total / launches,
            "fp64_tflops_achieved": (round(flops_total / (ms * 1e-3) / 1e12, 2)
