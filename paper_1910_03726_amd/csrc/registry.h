@@ -40,9 +40,9 @@ struct KernelTable {
   KernelFn bounded_tiled[2][8] = {};
   BatchFn bounded_tiled_b[2][8] = {};
 };
-// points per thread chunk by window width: odd, so lanes K doubles apart hit
-// distinct LDS banks; fewer for wide windows (register pressure)
-constexpr int bounded_k(int W) { return W >= 32 ? 5 : 9; }
+// points per thread chunk (any window width): odd, so lanes K doubles apart
+// hit distinct LDS banks
+constexpr int bounded_k(int) { return 9; }
 // inflow forcing rows the register-blocked kernel stages in LDS at a time
 constexpr int kFRowsLds = 64;
 constexpr int kNumBoundedWidths = 8;
