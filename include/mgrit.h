@@ -225,7 +225,9 @@ int mgrit_plan_create(mgrit_plan_t* plan, int nx, int nt, double alpha,
  *         dropped; offsets taken in (-n_x/2, n_x/2]).
  * The coarsest level is swept (no spectral solve: Psi is not circulant).
  * phi_apply_batch on such a plan steps every row from t = 0 with the
- * plan's inflow data (k <= n_t).  Other arguments and errors as
+ * plan's inflow data (k <= n_t).  The plan also holds the forcing table
+ * (n_t rows of at most s r_l FP64 values, s stages, r_l the upwind reach of
+ * Up), which mgrit_plan_estimate_bytes does not count.  Other arguments and errors as
  * mgrit_plan_create; n_x up to 10232 (two FP64 rows in a CU's 160 KB of
  * LDS). */
 int mgrit_plan_create_inflow(mgrit_plan_t* plan, int nx, int nt, double alpha,
