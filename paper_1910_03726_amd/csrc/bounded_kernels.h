@@ -191,8 +191,10 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
 #pragma unroll
     for (int i = 0; i < W; ++i) c[i] = a.taps[i];
   }
-  // boundary row of this thread (fine level), or -1
-  const int brow = tid < bd.nl ? tid : (tid < bd.nl + bd.nr ? nx - bd.nr + (tid - bd.nl) : -1);
+  // boundary rows (fine level): four consecutive threads share a row, each
+  // summing every fourth column; brow is this thread's row or -1
+  const int bq = tid >> 2, bpart = tid & 3;
+  const int brow = bq < bd.nl ? bq : (bq < bd.nl + bd.nr ? nx - bd.nr + (bq - bd.nl) : -1);
   // inflow forcing rows, staged in LDS kFRows steps at a time
   double* fst = rb + bd.nr * rst;
   const double* Fb = bd.F ? bd.F + (long long)j * a.omin * bd.nf : nullptr;
@@ -248,22 +250,27 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
         }
       }
     }
-    if (brow >= 0) {
+    if (bd.nl + bd.nr > 0) {  // uniform: every lane takes part in the quad sums
       double acc = 0.0;
-      if (brow < bd.nl) {
+      if (brow >= 0 && brow < bd.nl) {
         const double* row = lb + brow * lst;
-#pragma unroll 4
-        for (int q = 0; q < bd.ncl; ++q) acc = fma(row[q], cur[q], acc);
-      } else {
+#pragma unroll 2
+        for (int q = bpart; q < bd.ncl; q += 4) acc = fma(row[q], cur[q], acc);
+      } else if (brow >= 0) {
         const double* row = rb + (brow - (nx - bd.nr)) * rst;
         const double* src = cur + (nx - bd.ncr);
-#pragma unroll 4
-        for (int q = 0; q < bd.ncr; ++q) acc = fma(row[q], src[q], acc);
+#pragma unroll 2
+        for (int q = bpart; q < bd.ncr; q += 4) acc = fma(row[q], src[q], acc);
       }
-      if (Fb && brow < bd.nf) acc += fst[((s - 1) % kFRows) * bd.nf + brow];
-      if (has_g) acc += g[brow];
-      nxt[brow] = acc;
-      if (orow) orow[brow] = acc;
+      // quad sum in a fixed order (lanes 4i..4i+3 of one wavefront)
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (brow >= 0 && bpart == 0) {
+        if (Fb && brow < bd.nf) acc += fst[((s - 1) % kFRows) * bd.nf + brow];
+        if (has_g) acc += g[brow];
+        nxt[brow] = acc;
+        if (orow) orow[brow] = acc;
+      }
     }
     // next step's right-hand side for the first chunk, in flight across
     // the barrier

@@ -378,7 +378,7 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
   const int kb = wi >= 0 ? bounded_k(kBoundedWidths[wi]) : 1;
   const int nch = (nx + kb - 1) / kb;
   int rc;
-  // (one thread per boundary row, the rows staged in LDS after the state;
+  // (four threads per boundary row, the rows staged in LDS after the state;
   // zero padding around the state covers every window read)
   const int nbrows = fine ? fine->nl + fine->nr : 0;
   const int Wt = wi >= 0 ? kBoundedWidths[wi] : 0;
@@ -390,7 +390,7 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
                                     (size_t)kFRowsLds * fine->nf
                               : 0));
   const int pf = fine ? 0 : 1;  // coarse levels add a right-hand side row every step
-  if (nnz && wi >= 0 && kt.bounded_tiled[pf][wi] && nbrows <= 512 &&
+  if (nnz && wi >= 0 && kt.bounded_tiled[pf][wi] && 4 * nbrows <= 512 &&
       tiled_lds <= kernel_info(kt.bounded_tiled[pf][wi]).max_lds) {
     const int Wb = kBoundedWidths[wi];
     std::vector<double> dense(Wb, 0.0);
@@ -398,7 +398,7 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
     const int one = omx;
     fn[0] = kt.bounded_tiled[pf][wi];
     bfn[0] = kt.bounded_tiled_b[pf][wi];
-    NL = std::min(512, (std::max(nch, nbrows) + 63) / 64 * 64);
+    NL = std::min(512, (std::max(nch, 4 * nbrows) + 63) / 64 * 64);
     shmem[0] = shmem[1] = tiled_lds;
     ntaps = Wb;
     width = W;
