@@ -767,15 +767,20 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
 
 // Modelled time of one spectral coarsest-level solve of n steps (row
 // transforms, mode recurrences, inverse transforms), fitted to MI355X
-// traces: launch costs, about 3.5 us per four-stage pass of a transform, a
-// dependent load round trip of about 1.2 us per 16 steps of the
-// recurrences, 80 bytes of HBM traffic per point and step.
+// measurements (4096-point rows x 32 steps, 2048 x 512, 8192 x 16, within
+// about 10 %): launch costs, about 3.4 us per four-stage pass of a
+// transform per group of 16 points a thread takes, a dependent load round
+// trip of about 1.2 us per 16 steps of the recurrences, 64 bytes of HBM
+// traffic per point and step at 6 TB/s.
 static double spectral_time_us(int nx, int n) {
   int lg = 0;
   while ((1 << lg) < nx) ++lg;
   const int passes = (lg + 3) / 4;
-  return 3 * 3.0 + 2 * (4.0 + 3.5 * passes) + 2.0 + ((n + 15) / 16) * 1.2 +
-         (double)(n + 1) * nx * 80.0 / 3.0e6;
+  // a row transform: per pass, each of the 256 threads takes ceil(nx/4096)
+  // groups of 16 points (3.4 us per group and pass); rows run in parallel
+  const int groups = (nx + 4095) / 4096;
+  return 3 * 3.0 + 2 * (3.4 * passes * groups) + 2.0 + ((n + 15) / 16) * 1.2 +
+         (double)(n + 1) * nx * 64.0 / 6.0e6;
 }
 
 int Plan::set_coarse_mode(int mode) {
