@@ -129,8 +129,8 @@ __device__ __forceinline__ void lds_barrier() {
 // registers; the state buffers carry padl / padr zero points on either side
 // (BoundedDev), so those reads need no bounds checks.  K is odd, so lanes
 // whose chunks start K doubles apart read distinct LDS banks.  The dense
-// boundary rows of the fine level are staged in LDS at the start and
-// computed one row per thread.  The inflow forcing is staged in LDS for
+// boundary rows of the fine level are staged in LDS at the start; each is
+// summed by four lanes (a quarter of the dependent chain).  The inflow forcing is staged in LDS for
 // kFRows steps at a time; with PF (levels with a right-hand side every
 // step) the right-hand side rows of a thread's first chunk are loaded at
 // the end of the step before their use.  Steps are separated by LDS-only
