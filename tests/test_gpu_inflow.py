@@ -66,6 +66,9 @@ CASES = [
     ("ERK3", 200, 800, 4, 3, "F", "FCF", None),
     ("ERK3", 128, 512, 4, 2, "V", "F", None),
     ("ERK5", 1024, 1024, 4, 4, "V", "FCF", None),
+    # grids smaller than the two boundary blocks: Phi stored densely
+    ("ERK3", 24, 96, 4, 2, "V", "FCF", None),
+    ("ERK5", 48, 192, 4, 2, "V", "FCF", None),
 ]
 
 
