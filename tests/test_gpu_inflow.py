@@ -193,7 +193,7 @@ def test_several_chunks_per_thread():
     d, c, H, psi, G = _setup(s, nx, nt, m, L)
     u0 = np.sin(np.pi * (d.x + 1.0)) ** 4
     with M.Plan(nx, nt, c, s, m, L, psi, inflow=G) as P:
-        assert "bounded<K=9" in P.describe()
+        assert "bounded<K=" in P.describe()
         r = P.solve(torch.tensor(u0, device="cuda"), None, tol=1e-12, maxit=60, out="final")
     assert r.status == M.OK
     ref = d.time_stepping(u0, G, every=nt)[-1]
