@@ -240,10 +240,11 @@ def build_hierarchy_bound(disc, m, levels, nt, target=1e-3, max_width=64):
     Level by level (Psi_{l+1} against Phi_l^m, Sec. 4.4) the contiguous
     window of phi~^m is placed as by the window rule (best_window), and its
     width is the narrowest from the window rule's width up to max_width for
-    which max_two_level_bound(lambda_l, mu, m, n_l) <= target (n_l the steps
-    of level l, n_1 = nt); if none reaches the target, the width with the
-    smallest bound (the first on ties).  Returns dicts as build_hierarchy,
-    with the level's "bound".
+    which max_two_level_bound(lambda_l, mu, m, n_l) <= max(target, 1e-10)
+    (n_l the steps of level l, n_1 = nt; bounds below 1e-10 are at the
+    rounding level of the fit and meet any target); if none does, the
+    narrowest width whose bound is within 0.1 % of the smallest.  Returns
+    dicts as build_hierarchy, with the level's "bound".
     """
     n = disc.nx
     lam = disc.eigenvalues()
@@ -253,7 +254,7 @@ def build_hierarchy_bound(disc, m, levels, nt, target=1e-3, max_width=64):
     for _ in range(1, levels):
         col, _ = phi_m_first_column(lam, m)
         w0 = window_rule_width(col, nnz_prev)
-        best = None
+        cands = []
         pick = None
         for width in range(w0, max(w0, min(max_width, n)) + 1):
             offs = best_window(col, width)
@@ -262,12 +263,13 @@ def build_hierarchy_bound(disc, m, levels, nt, target=1e-3, max_width=64):
             b = max_two_level_bound(lam, mu, m, nl)
             cand = {"offsets": np.asarray(offs), "weights": psi, "max_imag": im,
                     "eigs": mu, "bound": b}
-            if b <= target:
+            cands.append(cand)
+            if b <= max(target, 1e-10):
                 pick = cand
                 break
-            if best is None or b < best["bound"]:
-                best = cand
-        pick = pick if pick is not None else best
+        if pick is None:
+            bmin = min(c["bound"] for c in cands)
+            pick = next(c for c in cands if c["bound"] <= (1.0 + 1e-3) * bmin)
         out.append(pick)
         lam = pick["eigs"]
         nnz_prev = len(pick["offsets"])

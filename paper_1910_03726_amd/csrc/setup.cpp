@@ -691,35 +691,37 @@ int psi_hierarchy_bound(int scheme, double cfl, int nx, int nt, int m, int level
     for (int k = 0; k < nx; ++k) rcol[k] = col[k].real();
     const int w0 = std::max(nnz_prev, cyclic_span(threshold(rcol, 0.02), nx));
     const int w1 = std::max(w0, std::min(max_width, nx));
-    Taps best, pick;
-    std::vector<cd> best_mu, pick_mu;
-    double best_b = 0.0, pick_b = 0.0;
-    bool have_best = false, have_pick = false;
-    for (int W = w0; W <= w1 && !have_pick; ++W) {
+    // bounds below kBoundFloor are at the rounding level of the fit: such a
+    // width meets any target; without one, the narrowest width within
+    // kBoundTie of the smallest bound
+    constexpr double kBoundFloor = 1e-10, kBoundTie = 1e-3;
+    const double T = std::max(target, kBoundFloor);
+    std::vector<Taps> cand;
+    std::vector<std::vector<cd>> cand_mu;
+    std::vector<double> cand_b;
+    int chosen = -1;
+    for (int W = w0; W <= w1 && chosen < 0; ++W) {
       Taps tp;
       tp.off = best_window(rcol, W);
       max_imag = std::max(max_imag, lsq_psi(lam, m, tp.off, tp.w));
       std::vector<cd> mu;
       taps_eigs(tp, nx, mu);
       const double b = two_level_bound_max(lam, mu, m, n);
-      if (b <= target) {
-        pick = tp;
-        pick_mu.swap(mu);
-        pick_b = b;
-        have_pick = true;
-      } else if (!have_best || b < best_b) {
-        best = tp;
-        best_mu.swap(mu);
-        best_b = b;
-        have_best = true;
-      }
+      cand.push_back(tp);
+      cand_mu.push_back(std::move(mu));
+      cand_b.push_back(b);
+      if (b <= T) chosen = (int)cand.size() - 1;
     }
-    if (!have_pick) {
-      if (!have_best) return MGRIT_EINVAL;
-      pick = best;
-      pick_mu.swap(best_mu);
-      pick_b = best_b;
+    if (chosen < 0) {
+      if (cand.empty()) return MGRIT_EINVAL;
+      const double bmin = *std::min_element(cand_b.begin(), cand_b.end());
+      for (size_t i = 0; i < cand_b.size() && chosen < 0; ++i)
+        if (cand_b[i] <= (1.0 + kBoundTie) * bmin) chosen = (int)i;
     }
+    Taps pick = cand[chosen];
+    std::vector<cd> pick_mu;
+    pick_mu.swap(cand_mu[chosen]);
+    const double pick_b = cand_b[chosen];
     nnz_prev = (int)pick.off.size();
     lam.swap(pick_mu);
     out.push_back(pick);

@@ -122,6 +122,18 @@ def test_psi_optimize_bound_matches_oracle(scheme, nx, nt, m, L, target):
         assert b == pytest.approx(h["bound"], rel=1e-6, abs=1e-10)
 
 
+def test_psi_optimize_bound_unreachable_target_takes_the_smallest_bound():
+    # no width reaches 1e-15: each level takes the width of smallest bound
+    s, nx, nt, m, L = "ERK3", 128, 2048, 4, 3
+    c = rk.paper_cfl(s)
+    got, bounds, _ = M.psi_optimize_bound(s, c, nx, nt, m, L, 1e-15)
+    H = coarse.build_hierarchy_bound(rk.Discretization(s, nx, c), m, L, nt, 1e-15)
+    for (o, _), b, h in zip(got, bounds, H):
+        assert sorted(o.tolist()) == sorted(h["offsets"].tolist())
+        assert b > 1e-15
+        assert b == pytest.approx(h["bound"], rel=1e-6, abs=1e-10)
+
+
 def test_psi_optimize_bound_rejects_sdirk():
     with pytest.raises(M.MgritError):
         M.psi_optimize_bound("SDIRK3", 4.0, 256, 1024, 4, 2)
