@@ -181,9 +181,9 @@ int mgrit_psi_optimize(int scheme, double cfl, int nx, int m, int levels,
  *     max_k sqrt(m) |lambda_k|^m |lambda_k^m - mu_k| sum_{j < n_l/m - 1} |mu_k|^j
  * (n_l the steps of level l, n_1 = nt) is at most max(target, 1e-10)
  * (bounds below 1e-10 are at the rounding level of the fit), else the
- * narrowest width whose bound is within 0.1 % of the smallest.  Wider coarse stencils cost the relaxation
- * kernels little (their passes are bound by memory traffic and latency) and
- * save iterations.  Each candidate width is one weighted least-squares
+ * narrowest width whose bound is within 0.1 % of the smallest.  Wider
+ * coarse stencils cost the relaxation kernels little (their passes are
+ * bound by memory traffic and latency) and save iterations.  Each candidate width is one weighted least-squares
  * solve (eq. (9)), so this setup takes tens of milliseconds per level at
  * n_x = 8192.  out as for mgrit_psi_optimize (room for up to
  * MGRIT_PSI_BOUND_MAX_WIDTH taps per level); bounds (may be NULL) receives
