@@ -225,6 +225,14 @@ int mgrit_plan_create(mgrit_plan_t* plan, int nx, int nt, double alpha,
  *         truncated to the interval (terms with i - offset outside 0..n_x-1
  *         dropped; offsets taken in (-n_x/2, n_x/2]).
  * The coarsest level is swept (no spectral solve: Psi is not circulant).
+ * When every offset of the truncated coarsest Psi is >= 1, Psi is strictly
+ * lower triangular and Psi^q = 0 for q = ceil(n_x / smallest offset); a
+ * step then depends on the last q states only, and with
+ * MGRIT_COARSE_AUTO (the default) the sweep runs in parallel chunks of q
+ * steps, each started from zero q steps before its first stored row
+ * (mgrit_plan_describe: "(chunked sweep)"), giving the step-by-step
+ * sweep's values bit for bit; MGRIT_COARSE_SWEEP keeps the step-by-step
+ * sweep.
  * phi_apply_batch on such a plan steps every row from t = 0 with the
  * plan's inflow data (k <= n_t).  The plan also holds the forcing table
  * (n_t rows of at most s r_l FP64 values, s stages, r_l the upwind reach of

@@ -135,6 +135,7 @@ __device__ __forceinline__ void lds_barrier() {
 // step) the right-hand side rows of a thread's first chunk are loaded at
 // the end of the step before their use.  Steps are separated by LDS-only
 // barriers, so those loads stay in flight across them.
+// Also runs MODE_FW (common.h): the coarsest sweep in overlapping chunks.
 // LDS: state and next state (each padl + n_x + padr), the left and right
 // blocks, then kFRows forcing rows.
 template <int K, int W, bool PF>
@@ -145,6 +146,12 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
   const int nx = a.nx, m = a.m, NT = blockDim.x, tid = threadIdx.x;
   const int omax = a.tap_off[0];
   const int nch = (nx + K - 1) / K;
+  // rows of this block: steps 1..nsteps write rows rbase + s
+  const bool fw = a.mode == MODE_FW;
+  const int t0 = fw ? max(0, j * m - a.tile) : 0;
+  const int warm = fw ? j * m - t0 : 0;
+  const int nsteps = fw ? warm + min(m, a.nint - j * m) : m;
+  const long long rbase = fw ? (long long)t0 : (long long)j * m;
   const int span = bd.padl + nx + bd.padr;
   double* bufa = reinterpret_cast<double*>(smem_raw);
   double* cur = bufa + bd.padl;
@@ -163,7 +170,8 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
     const double* in = a.zero_in ? nullptr : a.in + (long long)j * a.in_stride * nx;
     const double* co = (a.zero_in || !a.corr) ? nullptr : a.corr + (long long)j * a.corr_stride * nx;
     double* o0 = a.mode == MODE_F ? a.out + (long long)j * m * nx
-                                  : ((a.mode == MODE_FC && a.write_row0 && j == 0) ? a.out : nullptr);
+                                  : (((a.mode == MODE_FC && a.write_row0) || fw) && j == 0 ? a.out
+                                                                                    : nullptr);
     for (int p0 = tid; p0 < nx; p0 += BL * NT) {
       double v[BL], c2[BL];
 #pragma unroll
@@ -205,14 +213,14 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
   if (PF && has_g) {
 #pragma unroll
     for (int k = 0; k < KP; ++k)
-      gnext[k] = (m >= 1 && b0 + k < nx) ? a.rhs[((long long)j * m + 1) * nx + b0 + k] : 0.0;
+      gnext[k] = (nsteps >= 1 && b0 + k < nx) ? a.rhs[(rbase + 1) * nx + b0 + k] : 0.0;
   }
-  for (int s = 1; s <= m; ++s) {
-    const double* g = has_g ? a.rhs + ((long long)j * m + s) * nx : nullptr;
-    const bool store = a.mode == MODE_F && (s < m || a.write_last);
-    double* orow = store ? a.out + ((long long)j * m + s) * nx : nullptr;
+  for (int s = 1; s <= nsteps; ++s) {
+    const double* g = has_g ? a.rhs + (rbase + s) * nx : nullptr;
+    const bool store = (a.mode == MODE_F && (s < m || a.write_last)) || (fw && s > warm);
+    double* orow = store ? a.out + (rbase + s) * nx : nullptr;
     if (Fb && (s - 1) % kFRows == 0) {
-      const int rows = min(kFRows, m - (s - 1));
+      const int rows = min(kFRows, nsteps - (s - 1));
       for (int q = tid; q < rows * bd.nf; q += NT) fst[q] = Fb[(long long)(s - 1) * bd.nf + q];
       __syncthreads();
     }
@@ -274,7 +282,7 @@ __device__ __forceinline__ void bounded_tiled_body(const RelaxArgs& a, const int
     }
     // next step's right-hand side for the first chunk, in flight across
     // the barrier
-    if (PF && has_g && s < m) {
+    if (PF && has_g && s < nsteps) {
 #pragma unroll
       for (int k = 0; k < KP; ++k) gnext[k] = b0 + k < nx ? g[nx + b0 + k] : 0.0;
     }

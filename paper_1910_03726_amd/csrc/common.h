@@ -17,6 +17,12 @@ enum RelaxMode : int {
   MODE_RES = 1,  // F-relaxation + C-point residual: out[j+1] = g + Phi^m start_j - ref[j+1]
   MODE_F = 2,    // F-relaxation writing every point: out[j*m + s], s = 0..m-1
                  // (the extra block j == nint writes its start state only)
+  MODE_FW = 3,   // bounded kernel, a sweep of nint steps in chunks of m:
+                 // block j steps from zero at row t0 = max(0, j*m - tile)
+                 // up to row min((j+1)*m, nint), storing rows > j*m (and
+                 // row 0 = 0 in block 0); exact when the operator vanishes
+                 // after `tile` applications (truncated stencils whose
+                 // offsets are all >= 1)
 };
 
 // How the right-hand side g of the level's system enters the steps.

@@ -405,6 +405,9 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
     Wbucket = Wb;
     rc = upload((void**)&d_taps, dense.data(), dense.size() * sizeof(double));
     if (!rc) rc = upload((void**)&d_off, &one, sizeof(int));
+    // truncated, strictly lower triangular (every offset >= 1): nilpotent,
+    // Psi^q = 0 once q * (smallest offset) >= n_x
+    if (!fine && omn >= 1) nilq = (nx + omn - 1) / omn;
   } else {
     fn[0] = kt.bounded;
     bfn[0] = kt.bounded_b;
@@ -494,10 +497,11 @@ std::string OpDesc::describe() const {
     snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
   else if (kind == OP_BOUNDED)
   {
-    char kw[32] = "";
+    char kw[32] = "", nq[32] = "";
     if (Wbucket) snprintf(kw, sizeof kw, "<K=%d,W=%d>", bounded_k(Wbucket), Wbucket);
-    snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s", kw, ntaps, NL,
-             d_extra.empty() ? "" : " +boundary rows");
+    if (nilq) snprintf(nq, sizeof nq, " nilpotent q=%d", nilq);
+    snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s%s", kw, ntaps, NL,
+             d_extra.empty() ? "" : " +boundary rows", nq);
   }
   else
     snprintf(buf, sizeof buf, "sdirk<K=%d> NL=%d", K, NL);
@@ -670,6 +674,22 @@ int Plan::copy_cpoints(int l, int prec, const double* in, long long in_stride,
 int Plan::sequential_chunk(int s0, const double* g, bool* last) {
   Level& L = lev.back();
   const OpDesc& op = L.seq;
+  if (chunked && s0 == 0) {
+    // nilpotent truncated Psi: a step depends on the states of the last
+    // nilq steps only, so chunks of nilq steps run in parallel, each from
+    // zero nilq steps before its first row (the same values bit for bit)
+    RelaxArgs a = base_args(*this, op);
+    a.zero_in = 1;
+    a.rhs = g;
+    a.rhs_mode = RHS_EVERY;
+    a.mode = MODE_FW;
+    a.m = op.nilq;
+    a.tile = op.nilq;
+    a.nint = L.n;
+    a.out = L.X;
+    *last = true;
+    return launch(op, 0, a, (L.n + op.nilq - 1) / op.nilq, MGRIT_PROF_COARSEST);
+  }
   const int S = op.seq_chunk > 0 ? op.seq_chunk : L.n;
   RelaxArgs a = base_args(*this, op);
   if (s0 == 0) {
@@ -790,7 +810,11 @@ int Plan::set_coarse_mode(int mode) {
   coarse_mode = mode;
   spectral = Sspec && (mode == MGRIT_COARSE_SPECTRAL ||
                        (mode == MGRIT_COARSE_AUTO && spectral_us < lev.back().seq.seq_us));
-  description = description_levels + (spectral ? " (spectral solve)" : "");
+  const OpDesc& cs = lev.back().seq;
+  chunked = mode == MGRIT_COARSE_AUTO && cs.kind == OP_BOUNDED && cs.nilq > 0 &&
+            2 * cs.nilq < lev.back().n;
+  description = description_levels + (spectral ? " (spectral solve)" : "") +
+                (chunked ? " (chunked sweep)" : "");
   return MGRIT_OK;
 }
 }  // namespace mgr

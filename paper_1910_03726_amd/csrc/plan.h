@@ -56,6 +56,8 @@ struct OpDesc {
   int* d_off = nullptr;
   void* d_sdirk = nullptr;
   void* d_bnd = nullptr;                // bounded kernel: device BoundedDev
+  int nilq = 0;                         // bounded coarse operator with every offset
+                                        // >= 1: Psi^nilq = 0 (else 0)
   std::vector<void*> d_extra;           // bounded kernel: its blocks and forcing
   size_t bytes = 0;
   hipStream_t stream = nullptr;         // allocation and upload stream
@@ -136,6 +138,8 @@ struct Plan {
   // `spectral`) or chunked sweeps
   int coarse_mode = MGRIT_COARSE_AUTO;
   bool spectral = false;
+  // inflow plans: the coarsest sweep in overlapping chunks (nilpotent Psi)
+  bool chunked = false;
   double* Sspec = nullptr;
   double spectral_us = 0.0;
   int set_coarse_mode(int mode);

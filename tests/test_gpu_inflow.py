@@ -199,3 +199,23 @@ def test_several_chunks_per_thread():
     ref = d.time_stepping(u0, G, every=nt)[-1]
     assert np.max(np.abs(r.out.cpu().numpy()[0] - ref)) <= 1e-10
 
+
+def test_chunked_coarsest_sweep_equals_the_sweep_bit_for_bit():
+    # the truncated coarsest Psi of the 4096 x 16384 ERK3 V-cycle has every
+    # offset >= 1, so Psi^q = 0: the chunked sweep gives the same values
+    s, nx, nt, m, L = "ERK3", 4096, 16384, 8, 4
+    d, c, H, psi, G = _setup(s, nx, nt, m, L)
+    u0 = torch.tensor(np.sin(np.pi * (d.x + 1.0)) ** 4, device="cuda")
+    res = {}
+    with M.Plan(nx, nt, c, s, m, L, psi, inflow=G) as P:
+        assert "(chunked sweep)" in P.describe()
+        for mode in ("auto", "sweep"):
+            P.set_coarse_solver(mode)
+            assert ("(chunked sweep)" in P.describe()) == (mode == "auto")
+            P.set_seed(4)
+            res[mode] = P.solve(u0, None, tol=1e-12, maxit=60, out="cpoints")
+    a, b = res["auto"], res["sweep"]
+    assert a.status == b.status == M.OK
+    assert a.iters == b.iters and a.hist == b.hist
+    assert torch.equal(a.out, b.out)
+
