@@ -137,3 +137,31 @@ def test_table5_erk1_counts():
         R = M.solve(u0, inputs.random_iterate(257, 256, 1), 1e-10, 40, mgrit.norm_scale(d),
                     g=d.rhs(u0, G))
         assert R.iters == want[L - 2], L
+
+
+def test_truncated_psi_with_positive_offsets_is_nilpotent_and_chunks_are_exact():
+    # every offset >= 1: Psi is strictly lower triangular, Psi^q = 0 for
+    # q = ceil(n_x / smallest offset); the sweep x^s = Psi x^(s-1) + g^s
+    # restarted from zero q steps before a row gives that row exactly
+    nx, offs = 40, np.array([3, 4, 5, 6, 8])
+    w = np.random.default_rng(4).standard_normal(len(offs))
+    op = inflow.truncated_taps_op(offs, w)
+    q = -(-nx // int(offs.min()))
+    E = np.eye(nx)
+    Pq = E
+    for _ in range(q):
+        Pq = op(Pq)
+    assert np.all(Pq == 0.0)
+    Pq1 = E
+    for _ in range(q - 1):
+        Pq1 = op(Pq1)
+    assert np.any(Pq1 != 0.0)  # q is the nilpotency index here
+    n = 50
+    g = np.random.default_rng(5).standard_normal((n + 1, nx))
+    g[0] = 0.0
+    ref = mgrit.sequential_solve(op, g)
+    for t in range(q, n + 1):
+        x = np.zeros(nx)
+        for s in range(t - q + 1, t + 1):
+            x = op(x[None])[0] + g[s]
+        assert np.array_equal(x, ref[t]), t
