@@ -50,6 +50,8 @@ extern "C" {
 #define MGRIT_ENODEV (-8)     /* no usable gfx950 device                      */
 #define MGRIT_ECAPACITY (-9)  /* caller's output arrays are too small         */
 #define MGRIT_EBUSY (-10)     /* serving: admission refused (HBM budget)      */
+#define MGRIT_ESCRATCH (-11)  /* mgrit_solve_static: plan exceeds the static
+                                 workspace (MGRIT_STATIC_BYTES)              */
 
 /* ---- discretizations (Sec. 2.1; tableaux of Appendix A) ----------------- */
 #define MGRIT_ERK1 1
@@ -345,6 +347,42 @@ const char* mgrit_plan_describe(mgrit_plan_t plan);
 
 /* Release the plan and its device memory (NULL is a no-op). */
 void mgrit_destroy(mgrit_plan_t plan);
+
+/* ---- allocation-free solve ------------------------------------------------ */
+
+/* Bytes of the static per-device workspace of mgrit_solve_static. */
+#define MGRIT_STATIC_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solve of mgrit_plan_create + mgrit_solve + mgrit_destroy with the same
+ * arguments and results, bit for bit, but with every device array of the
+ * plan (C-point iterates, residuals, coarse-level arrays, per-workgroup
+ * partial sums, the norm word, taps, stage data and spectral rows) carved
+ * from one static array of MGRIT_STATIC_BYTES that the library reserves
+ * on each GPU it runs on until the process ends.  No hipMalloc, hipFree or
+ * pinned host allocation happens in the call (host bookkeeping uses the
+ * C++ heap).
+ *   Arguments: as mgrit_plan_create (the plan's inputs; inflow boundaries
+ *   are not offered here) followed by those of mgrit_solve; the work runs
+ *   on hip_stream and the call returns after it has finished.
+ *   Errors: those of mgrit_plan_create and mgrit_solve, and
+ *   MGRIT_ESCRATCH when the plan's arrays do not fit the workspace (the
+ *   space-time arrays take about 3 (n_t/m + 1) n_x doubles plus the coarse
+ *   levels; nothing is launched then).
+ *   Sharing: every call on a GPU uses that GPU's one workspace, which keeps
+ *   the last call's contents (nothing in it is assumed to start at zero).
+ *   Calls on the same device are serialized by the library (a call holds
+ *   the device's workspace until its GPU work has finished), so callers on
+ *   several threads or streams of one GPU wait for each other rather than
+ *   race; work outside these calls that writes the workspace's memory is
+ *   not possible, since its address never leaves the library. */
+int mgrit_solve_static(int nx, int nt, double alpha, double cfl, int scheme,
+                       int m, int levels, const mgrit_taps* psi, int cycle,
+                       int relax, int precision, void* hip_stream,
+                       const double* u0_dev, const double* uinit_dev,
+                       double tol, int maxit, double* u_out_dev,
+                       int out_kind, double* res_hist_host, int* iters_out);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,7 @@ def _jobs():
     objs.append((HIPCC, os.path.join(CSRC, "serve.cpp"), "serve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "solve.cpp"), "solve.o", ["-x", "hip"]))
     objs.append((HIPCC, os.path.join(CSRC, "misc.hip"), "misc.o", []))
+    objs.append((HIPCC, os.path.join(CSRC, "static_solve.hip"), "static_solve.o", []))
     objs.append((HIPCC, os.path.join(CSRC, "spectral.hip"), "spectral.o", []))
     objs.append((HIPCC, os.path.join(CSRC, "inst_bounded.hip"), "inst_bounded.o", []))
     objs.append(("g++", os.path.join(CSRC, "inflow_setup.cpp"), "inflow_setup.o", []))

@@ -858,8 +858,27 @@ size_t size_class(size_t b) {
 }
 }  // namespace
 
+thread_local Arena* t_arena = nullptr;
+
+void set_thread_arena(Arena* a) { t_arena = a; }
+
+static bool in_arena(const void* p) {
+  const Arena* a = t_arena;
+  return a && (const char*)p >= a->base && (const char*)p < a->base + a->cap;
+}
+
 int dev_alloc(void** p, size_t bytes) {
   *p = nullptr;
+  if (Arena* a = t_arena) {
+    const size_t off = (a->used + 255) & ~(size_t)255;
+    if (off > a->cap || bytes > a->cap - off) {
+      a->overflow = true;
+      return MGRIT_ENOMEM;
+    }
+    *p = a->base + off;
+    a->used = off + bytes;
+    return MGRIT_OK;
+  }
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MGRIT_ENODEV;
   const size_t c = size_class(bytes);
@@ -889,7 +908,7 @@ int dev_alloc(void** p, size_t bytes) {
 }
 
 void dev_free(void* p) {
-  if (!p) return;
+  if (!p || in_arena(p)) return;
   {
     std::lock_guard<std::mutex> lk(g_blk_mu);
     auto it = g_blk_live.find(p);
@@ -925,6 +944,7 @@ std::mutex g_word_mu;
 std::vector<double*> g_free_words;
 
 static double* take_host_word() {
+  if (t_arena) return &t_arena->host_word;
   std::lock_guard<std::mutex> lk(g_word_mu);
   if (g_free_words.empty()) {
     constexpr int kSlab = 1024;
@@ -938,7 +958,7 @@ static double* take_host_word() {
 }
 
 static void give_host_word(double* w) {
-  if (!w) return;
+  if (!w || (t_arena && w == &t_arena->host_word)) return;
   std::lock_guard<std::mutex> lk(g_word_mu);
   g_free_words.push_back(w);
 }
@@ -965,6 +985,7 @@ const char* mgrit_strerror(int code) {
     case MGRIT_ENODEV: return "no usable gfx950 device";
     case MGRIT_ECAPACITY: return "output arrays too small";
     case MGRIT_EBUSY: return "admission refused: HBM budget";
+    case MGRIT_ESCRATCH: return "plan does not fit the static workspace of mgrit_solve_static";
     default: return "unknown error";
   }
 }

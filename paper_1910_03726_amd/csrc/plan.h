@@ -24,6 +24,19 @@ int dev_alloc(void** p, size_t bytes);
 void dev_free(void* p);
 void dev_trim();
 
+// While a calling thread has an arena set, dev_alloc hands out 256-byte
+// aligned pieces of [base, base + cap) instead of blocks of its own,
+// dev_free leaves pointers inside it alone, and a plan's norm word is the
+// arena's host_word: plans built that way allocate no device or pinned host
+// memory (the allocation-free solve, static_solve.hip).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool overflow = false;  // a request did not fit
+  double host_word = 0.0;
+};
+void set_thread_arena(Arena* a);  // nullptr: back to the block cache
+
 // One launch shape of the stencil kernel: `tiles` workgroups per interval,
 // each of NL lanes x K points, writing `tile` points.  A tiled shape
 // (tiles > 1) is valid for passes of at most `max_steps` steps (the tile's

@@ -25,7 +25,8 @@ PSI_RULES = {"auto": 0, "window": 1, "eta": 2, "redisc": 3}
 OUT = {"none": 0, "final": 1, "cpoints": 2, "all": 3}
 
 OK, EINVAL, EUNSTABLE, ENOMEM, EHIP, ENOTCONV, EDIVERGED, EIMAG, ENODEV, \
-    ECAPACITY, EBUSY = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
+    ECAPACITY, EBUSY, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10, -11
+STATIC_BYTES = 64 << 20  # MGRIT_STATIC_BYTES
 COARSE = {"auto": 0, "sweep": 1, "spectral": 2}
 PROF_CLASSES = ("relax_fine", "relax_coarse", "coarsest", "norm", "other")
 
@@ -153,6 +154,9 @@ _SIGS = {
     "mgrit_operator_complexity": (_I, [_P, ctypes.POINTER(_D)]),
     "mgrit_plan_describe": (ctypes.c_char_p, [_P]),
     "mgrit_destroy": (None, [_P]),
+    "mgrit_solve_static": (_I, [_I, _I, _D, _D, _I, _I, _I, ctypes.POINTER(Taps), _I, _I,
+                                _I, _P, _P, _P, _D, _I, _P, _I, ctypes.POINTER(_D),
+                                ctypes.POINTER(_I)]),
     "mgrit_plan_estimate_bytes": (_I, [_I, _I, _I, _I, _I,
                                        ctypes.POINTER(ctypes.c_size_t)]),
     "mgrit_server_create": (_I, [ctypes.POINTER(_P), ctypes.c_size_t, _I, _I, _I, _I]),
@@ -458,6 +462,47 @@ class Plan:
 
     def describe(self):
         return lib().mgrit_plan_describe(self._h).decode()
+
+
+def _taps_array(psi, levels):
+    arr = (Taps * max(1, levels - 1))()
+    keep = []
+    for i, (o, w) in enumerate(psi):
+        oa = (_I * len(o))(*[int(x) for x in o])
+        wa = (_D * len(w))(*[float(x) for x in w])
+        keep.append((oa, wa))
+        arr[i].nnz = len(o)
+        arr[i].offset = oa
+        arr[i].weight = wa
+    return arr, keep
+
+
+def solve_static(nx, nt, cfl, scheme, m, levels, psi, u0, uinit=None, tol=1e-10, maxit=100,
+                 out="final", u_out=None, alpha=1.0, cycle="V", relax="FCF",
+                 precision="fp64", stream=None):
+    """mgrit_solve_static: a plan's solve without device allocation in the
+    library (its arrays live in the static per-device workspace).  Returns
+    (status, iterations, residual history, u_out)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    nc = nt // m
+    rows = {"none": 0, "final": 1, "cpoints": nc + 1, "all": nt + 1}[out]
+    if out != "none" and u_out is None:
+        u_out = torch.empty((rows, nx), dtype=torch.float64, device=u0.device)
+    arr, keep = _taps_array(psi, levels)
+    hist = (_D * (maxit + 1))()
+    it = _I()
+    rc = lib().mgrit_solve_static(
+        nx, nt, alpha, cfl, _scheme(scheme), m, levels, arr, CYCLES[cycle], RELAX[relax],
+        PRECISION[precision], ctypes.c_void_p(stream), _ptr(u0, "u0", nx),
+        _ptr(uinit, "uinit", (nc + 1) * nx), tol, maxit,
+        _ptr(u_out, "u_out", rows * nx) if out != "none" else None, OUT[out], hist,
+        ctypes.byref(it))
+    del keep
+    if rc not in (OK, ENOTCONV, EDIVERGED):
+        raise MgritError(rc, "mgrit_solve_static")
+    return rc, it.value, list(hist[:it.value + 1]), u_out
 
 
 def estimate_bytes(nx, nt, m, levels, precision="fp64"):
