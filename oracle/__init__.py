@@ -1,4 +1,5 @@
-"""CPU FP64 oracle for MGRIT/Parareal on periodic linear advection.
+"""CPU oracle (FP64; Lemma 1's closed form in extended precision) for
+MGRIT/Parareal on periodic linear advection.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
 execute this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
@@ -12,8 +13,12 @@ plain, slow and meant to be checked by eye against the paper:
 
 * ``rk``     -- upwind stencils U1-U5 (Sec. 2.1), Butcher tableaux
                 (Appendix A, Tables 7 and 8), staged Runge-Kutta stepping
-                (eq. (3)), the stability function of Lemma 1 / eq. (4),
-                CFL limits (eq. (5), Table 1).
+                (eq. (3)), the stability function of Lemma 1 / eq. (4) and
+                the closed form Phi^n = F^-1 diag(lambda^n) F of Lemma 1 in
+                extended precision (the exact discrete solution over long
+                horizons), CFL limits (eq. (5), Table 1).  Stencil and
+                tableau entries are written once, as exact fractions or
+                formulas, and evaluated in FP64 and in extended precision.
 * ``coarse`` -- first column of Phi^m, the weighted least-squares coarse
                 operator of eqs. (8)-(9), sparsity-pattern rules (Sec. 4.3,
                 Sec. 4.6), operator complexity eq. (10), the two-level

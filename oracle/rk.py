@@ -21,69 +21,82 @@ import numpy as np
 
 # ---------------------------------------------------------------------------
 # Upwind stencils U1-U5 (Sec. 2.1, formulas tagged U1..U5).
-# Map: offset j -> coefficient d_j in  v'_i ~ (1/dx) sum_j d_j v_{i+j}.
+# Map: offset j -> coefficient d_j in  v'_i ~ (1/dx) sum_j d_j v_{i+j},
+# written as exact fractions (numerator, denominator).
 # ---------------------------------------------------------------------------
-UPWIND = {
-    1: {0: 1.0, -1: -1.0},
-    2: {0: 3.0 / 2.0, -1: -4.0 / 2.0, -2: 1.0 / 2.0},
-    3: {1: 2.0 / 6.0, 0: 3.0 / 6.0, -1: -6.0 / 6.0, -2: 1.0 / 6.0},
-    4: {1: 3.0 / 12.0, 0: 10.0 / 12.0, -1: -18.0 / 12.0, -2: 6.0 / 12.0,
-        -3: -1.0 / 12.0},
-    5: {2: -3.0 / 60.0, 1: 30.0 / 60.0, 0: 20.0 / 60.0, -1: -60.0 / 60.0,
-        -2: 15.0 / 60.0, -3: -2.0 / 60.0},
+UPWIND_FRACTIONS = {
+    1: {0: (1, 1), -1: (-1, 1)},
+    2: {0: (3, 2), -1: (-4, 2), -2: (1, 2)},
+    3: {1: (2, 6), 0: (3, 6), -1: (-6, 6), -2: (1, 6)},
+    4: {1: (3, 12), 0: (10, 12), -1: (-18, 12), -2: (6, 12), -3: (-1, 12)},
+    5: {2: (-3, 60), 1: (30, 60), 0: (20, 60), -1: (-60, 60), -2: (15, 60),
+        -3: (-2, 60)},
 }
+UPWIND = {p: {j: n / d for j, (n, d) in c.items()} for p, c in UPWIND_FRACTIONS.items()}
+
+LD = np.longdouble  # x86 extended precision: 64-bit significand
 
 
-def _tableau(rows, b):
-    s = len(b)
-    A = np.zeros((s, s))
-    for i, row in enumerate(rows):
-        A[i, :len(row)] = row
-    b = np.asarray(b, dtype=float)
-    return A, b, A.sum(axis=1)
+def _frac_ld(n, d):
+    return LD(n) / LD(d)
 
 
-def _sdirk3():
-    # Appendix A, Table 8: constants of the 3-stage, 3rd-order SDIRK method.
-    z = 0.43586652150845899942
-    al = (1.0 + z) / 2.0
-    be = (1.0 - z) / 2.0
-    ga = -1.5 * z * z + 4.0 * z - 0.25
-    ep = 1.5 * z * z - 5.0 * z + 1.25
-    A, b, c = _tableau([[z], [be, z], [ga, ep, z]], [ga, ep, z])
-    assert abs(c[1] - al) < 1e-15
-    return A, b, c
+def _tableaux(frac, sqrt, sdirk3_root, dtype):
+    """Butcher tableaux of Appendix A, Table 7 (ERK1-ERK5) and Table 8
+    (SDIRK1-SDIRK4), with every entry built by frac(p, q) = p/q, sqrt and the
+    SDIRK3 constant in one number type (FP64 or extended precision)."""
+    def tab(rows, b):
+        s = len(b)
+        A = np.zeros((s, s), dtype=dtype)
+        for i, row in enumerate(rows):
+            for j, v in enumerate(row):
+                A[i, j] = v
+        b = np.array(b, dtype=dtype)
+        return A, b, A.sum(axis=1)
+
+    f = frac
+    one, zero = f(1, 1), f(0, 1)
+    r2 = sqrt(2) / f(2, 1)
+    z = sdirk3_root
+    # SDIRK3 (Table 8): the other constants are polynomials in z
+    be = (one - z) / f(2, 1)
+    ga = f(-3, 2) * z * z + f(4, 1) * z - f(1, 4)
+    ep = f(3, 2) * z * z - f(5, 1) * z + f(5, 4)
+    return {
+        "ERK1": tab([[zero]], [one]),
+        "ERK2": tab([[zero], [one, zero]], [f(1, 2), f(1, 2)]),
+        "ERK3": tab([[zero], [one], [f(1, 4), f(1, 4)]], [f(1, 6), f(1, 6), f(2, 3)]),
+        "ERK4": tab([[zero], [f(1, 2)], [zero, f(1, 2)], [zero, zero, one]],
+                    [f(1, 6), f(1, 3), f(1, 3), f(1, 6)]),
+        "ERK5": tab(
+            [[zero],
+             [f(1, 4)],
+             [f(1, 8), f(1, 8)],
+             [zero, zero, f(1, 2)],
+             [f(3, 16), f(-3, 8), f(3, 8), f(9, 16)],
+             [f(-3, 7), f(8, 7), f(6, 7), f(-12, 7), f(8, 7)]],
+            [f(7, 90), zero, f(32, 90), f(12, 90), f(32, 90), f(7, 90)]),
+        "SDIRK1": tab([[one]], [one]),
+        "SDIRK2": tab([[one - r2], [r2, one - r2]], [r2, one - r2]),
+        "SDIRK3": tab([[z], [be, z], [ga, ep, z]], [ga, ep, z]),
+        "SDIRK4": tab(
+            [[f(1, 4)],
+             [f(1, 2), f(1, 4)],
+             [f(17, 50), f(-1, 25), f(1, 4)],
+             [f(371, 1360), f(-137, 2720), f(15, 544), f(1, 4)],
+             [f(25, 24), f(-49, 48), f(125, 16), f(-85, 12), f(1, 4)]],
+            [f(25, 24), f(-49, 48), f(125, 16), f(-85, 12), f(1, 4)]),
+    }
 
 
-_R2 = np.sqrt(2.0) / 2.0
+# The SDIRK3 diagonal (Table 8), to the 20 digits printed.
+SDIRK3_ROOT = "0.43586652150845899942"
 
-# Butcher tableaux: Appendix A, Table 7 (ERK1-ERK5) and Table 8 (SDIRK1-4).
-TABLEAUX = {
-    "ERK1": _tableau([[0.0]], [1.0]),
-    "ERK2": _tableau([[0.0], [1.0, 0.0]], [0.5, 0.5]),
-    "ERK3": _tableau([[0.0], [1.0], [0.25, 0.25]],
-                     [1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0]),
-    "ERK4": _tableau([[0.0], [0.5], [0.0, 0.5], [0.0, 0.0, 1.0]],
-                     [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),
-    "ERK5": _tableau(
-        [[0.0],
-         [1.0 / 4.0],
-         [1.0 / 8.0, 1.0 / 8.0],
-         [0.0, 0.0, 1.0 / 2.0],
-         [3.0 / 16.0, -3.0 / 8.0, 3.0 / 8.0, 9.0 / 16.0],
-         [-3.0 / 7.0, 8.0 / 7.0, 6.0 / 7.0, -12.0 / 7.0, 8.0 / 7.0]],
-        [7.0 / 90.0, 0.0, 32.0 / 90.0, 12.0 / 90.0, 32.0 / 90.0, 7.0 / 90.0]),
-    "SDIRK1": _tableau([[1.0]], [1.0]),
-    "SDIRK2": _tableau([[1.0 - _R2], [_R2, 1.0 - _R2]], [_R2, 1.0 - _R2]),
-    "SDIRK3": _sdirk3(),
-    "SDIRK4": _tableau(
-        [[1.0 / 4.0],
-         [1.0 / 2.0, 1.0 / 4.0],
-         [17.0 / 50.0, -1.0 / 25.0, 1.0 / 4.0],
-         [371.0 / 1360.0, -137.0 / 2720.0, 15.0 / 544.0, 1.0 / 4.0],
-         [25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 1.0 / 4.0]],
-        [25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 1.0 / 4.0]),
-}
+# FP64 tableaux (the staged stepper below) and extended-precision ones (the
+# closed form of Lemma 1, spectral_propagate).
+TABLEAUX = _tableaux(lambda p, q: p / q, lambda x: np.sqrt(float(x)), float(SDIRK3_ROOT),
+                     float)
+TABLEAUX_LD = _tableaux(_frac_ld, lambda x: np.sqrt(LD(x)), LD(SDIRK3_ROOT), LD)
 
 # CFL limits printed in Table 1 (ERKp+Up).
 CFL_MAX_TABLE1 = {1: 1.0, 2: 0.5, 3: 1.62589, 4: 1.04449, 5: 1.96583}
@@ -212,22 +225,49 @@ class Discretization:
         return self.stability_function(dt * self.symbol_L(theta))
 
     def spectral_propagate(self, u0, nsteps):
-        """Phi^n u0 in closed form: Phi is circulant with eigenvalues lambda_k
-        on the DFT modes (Lemma 1), so Phi^n u0 = F^{-1} diag(lambda^n) F u0.
+        """Phi^n u0 in closed form, in extended precision.
 
-        lambda^n is formed by repeated squaring; its relative rounding grows
-        like n * eps, so this is for long horizons where stepping is slow.
+        Phi is circulant with eigenvalue lambda_k = R(dt l(theta_k)) on the
+        DFT mode k (Lemma 1), so Phi^n u0 = F^{-1} diag(lambda^n) F u0.  The
+        whole evaluation runs in x86 extended precision (64-bit significand,
+        eps = 1.1e-19) from the exact stencil fractions and tableau entries:
+        the angles 2 pi (j k mod n_x)/n_x, the symbol, R(z) by forward
+        substitution (A is lower triangular), lambda^n by repeated squaring
+        (relative error ~ n eps) and the transforms; the result is rounded
+        to FP64 once.  It is the exact discrete solution of eq. (3) to
+        ~1e-14 relative for n <= 65536, where FP64 stepping drifts by the
+        rounding of its constants.
         """
-        lam = self.eigenvalues()
-        p = np.ones_like(lam)
-        base = lam.copy()
-        n = int(nsteps)
-        while n:
-            if n & 1:
+        n = self.nx
+        pi = np.arccos(LD(-1))
+        k = np.arange(n)
+        sym = np.zeros(n, dtype=np.clongdouble)
+        for j, (num, den) in UPWIND_FRACTIONS[self.p].items():
+            ang = (LD(2) * pi / LD(n)) * ((j * k) % n).astype(LD)
+            sym += _frac_ld(num, den) * (np.cos(ang) + 1j * np.sin(ang))
+        # dt l(theta) = -(alpha dt/dx) sum_j d_j e^{ij theta} = -c sum_j ...
+        z = -(LD(self.alpha) * LD(self.dt) / LD(self.dx)) * sym
+        A, b, _ = TABLEAUX_LD[self.scheme]
+        y = []
+        acc = np.zeros(n, dtype=np.clongdouble)
+        for i in range(len(b)):
+            r = np.ones(n, dtype=np.clongdouble)
+            for j in range(i):
+                if A[i, j] != 0:
+                    r = r + z * A[i, j] * y[j]
+            y.append(r / (1 - z * A[i, i]))
+            acc = acc + b[i] * y[i]
+        lam = 1 + z * acc
+        p = np.ones(n, dtype=np.clongdouble)
+        base = lam
+        e = int(nsteps)
+        while e:
+            if e & 1:
                 p = p * base
             base = base * base
-            n >>= 1
-        return np.real(np.fft.ifft(p * np.fft.fft(u0, axis=-1), axis=-1))
+            e >>= 1
+        U = np.fft.fft(np.asarray(u0, dtype=LD), axis=-1)
+        return np.real(np.fft.ifft(p * U, axis=-1)).astype(np.float64)
 
     def dense_phi(self):
         """Phi as a dense n_x x n_x matrix, built from the block form of the

@@ -190,3 +190,71 @@ def test_discretization_order(scheme):
         errs.append(np.sqrt(d.dx * np.sum((u - exact) ** 2)))
     rate = np.log2(errs[-2] / errs[-1])
     assert rate > p - 0.35, (scheme, errs, rate)
+
+
+# -- Lemma 1 closed form (spectral_propagate) ---------------------------------
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("scheme,nsteps", [("ERK1", 3000), ("ERK2", 2000), ("ERK3", 3000),
+                                           ("ERK4", 2000), ("ERK5", 3000), ("SDIRK1", 30),
+                                           ("SDIRK2", 500), ("SDIRK3", 500),
+                                           ("SDIRK4", 500)])
+def test_closed_form_matches_staged_stepping(scheme, nsteps):
+    # Lemma 1's Phi^n u0 against n stage-by-stage steps (a different
+    # algorithm: no eigenvalues, no transforms).  FP64 stepping drifts by
+    # ~eps per step; a dropped stage term, a wrong coefficient or a
+    # conjugated symbol would be off by O(1).  (SDIRK1 at c = 4 damps the
+    # modes below the rounding level within a few hundred steps: 30 steps.)
+    nx = 64
+    d = rk.Discretization(scheme, nx, rk.paper_cfl(scheme))
+    u0 = np.cos(np.pi * d.x) + 0.5 * np.sin(3 * np.pi * d.x) - 0.2 * np.cos(4 * np.pi * d.x)
+    assert _rel(d.spectral_propagate(u0, nsteps), d.propagate(u0, nsteps)) < 5e-16 * nsteps
+
+
+@pytest.mark.parametrize("scheme", ["ERK3", "ERK5", "SDIRK3", "SDIRK4"])
+def test_closed_form_matches_dense_phi_power(scheme):
+    # against the n-th power of Phi built from the block form of the step
+    nx, n = 16, 37
+    d = rk.Discretization(scheme, nx, rk.paper_cfl(scheme))
+    u0 = np.random.default_rng(9).standard_normal(nx)
+    P = np.linalg.matrix_power(d.dense_phi(), n)
+    # (the dense block solve rounds at the size of SDIRK4's entries, ~8)
+    assert _rel(d.spectral_propagate(u0, n), P @ u0) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["ERK3", "SDIRK3"])
+def test_closed_form_transports_to_the_right(scheme):
+    # u_t + alpha u_x = 0 with alpha > 0 carries a bump to the right by
+    # alpha t = n c dx: n c cells (Sec. 2.1)
+    nx = 256
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    u0 = np.exp(-((d.x + 0.5) / 0.08) ** 2)
+    n = 40
+    u = d.spectral_propagate(u0, n)
+    shift = (int(np.argmax(u)) - int(np.argmax(u0))) % nx
+    assert abs(shift - n * c) <= 1.0, (shift, n * c)
+
+
+def test_closed_form_is_extended_precision():
+    # one Fourier mode over 10^5 steps against a 40-digit evaluation of the
+    # same eigenvalue power: the FP64 closed form would be off by ~n eps
+    import mpmath as mp
+    mp.mp.dps = 40
+    nx, k, n = 1024, 1, 100000
+    scheme = "ERK3"
+    c = rk.paper_cfl(scheme)
+    d = rk.Discretization(scheme, nx, c)
+    u0 = np.cos(np.pi * k * d.x)
+    # R(z) = 1 + z + z^2/2 + z^3/6 for ERK3 (order 3, three stages)
+    th = 2 * mp.pi * k / nx
+    z = -mp.mpf(c) * sum(mp.mpf(num) / den * mp.exp(1j * j * th)
+                         for j, (num, den) in rk.UPWIND_FRACTIONS[3].items())
+    lam = 1 + z + z ** 2 / 2 + z ** 3 / 6
+    ln = lam ** n
+    want = np.array([float(mp.re(ln * mp.exp(1j * mp.pi * k * (mp.mpf(-1) + mp.mpf(2) * i / nx))))
+                     for i in range(nx)])
+    # n eps of extended precision is 1.1e-14; FP64 would give ~1e-11
+    assert _rel(d.spectral_propagate(u0, n), want) < 5e-14
