@@ -14,99 +14,157 @@ namespace mgr {
 static const double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
-// Appendix A: Butcher tableaux
+// Appendix A: Butcher tableaux, Sec. 2.1: upwind formulas
 // ---------------------------------------------------------------------------
-static void set_rows(Tableau& t, std::initializer_list<std::initializer_list<double>> rows,
-                     std::initializer_list<double> b) {
+// Every entry is written once, as a fraction p/q or a formula in sqrt(2) and
+// the SDIRK3 diagonal, and evaluated in the number type R: FP64 for the
+// kernels, extended precision or binary128 where the setup needs the exact
+// values (the collapsed ERK stencil, the SDIRK stage factorization).
+using quad = __float128;
+
+template <typename R>
+struct Num;
+template <>
+struct Num<double> {
+  static double sqrt2() { return std::sqrt(2.0); }
+  static double sdirk3_root() { return 0.43586652150845899942; }
+};
+template <>
+struct Num<long double> {
+  static long double sqrt2() { return std::sqrt(2.0L); }
+  static long double sdirk3_root() { return 0.43586652150845899942L; }
+};
+template <>
+struct Num<quad> {
+  static quad sqrt2() {
+    quad x = std::sqrt(2.0);  // two Newton steps from the FP64 root
+    for (int i = 0; i < 2; ++i) x = (x + quad(2) / x) / quad(2);
+    return x;
+  }
+  static quad sdirk3_root() {  // 0.4358665215 0845899942 (Table 8)
+    return (quad(4358665215LL) + quad(845899942LL) / quad(10000000000LL)) /
+           quad(10000000000LL);
+  }
+};
+
+template <typename R>
+struct TableauOf {
+  int s = 0;
+  R A[MAX_STAGES][MAX_STAGES] = {};
+  R b[MAX_STAGES] = {};
+};
+
+template <typename R>
+static void rows_of(TableauOf<R>& t, std::initializer_list<std::initializer_list<R>> rows,
+                    std::initializer_list<R> b) {
   int i = 0;
   for (auto& r : rows) {
     int j = 0;
-    for (double v : r) t.A[i][j++] = v;
+    for (R v : r) t.A[i][j++] = v;
     ++i;
   }
   t.s = (int)b.size();
   int k = 0;
-  for (double v : b) t.b[k++] = v;
+  for (R v : b) t.b[k++] = v;
+}
+
+template <typename R>
+static bool tableau_of(int scheme, TableauOf<R>& t) {
+  t = TableauOf<R>();
+  auto f = [](long long p, long long q) { return R(p) / R(q); };
+  const R one = R(1), zero = R(0);
+  switch (scheme) {
+    case MGRIT_ERK1:
+      rows_of<R>(t, {{zero}}, {one});
+      return true;
+    case MGRIT_ERK2:
+      rows_of<R>(t, {{zero}, {one, zero}}, {f(1, 2), f(1, 2)});
+      return true;
+    case MGRIT_ERK3:
+      rows_of<R>(t, {{zero}, {one}, {f(1, 4), f(1, 4)}}, {f(1, 6), f(1, 6), f(2, 3)});
+      return true;
+    case MGRIT_ERK4:
+      rows_of<R>(t, {{zero}, {f(1, 2)}, {zero, f(1, 2)}, {zero, zero, one}},
+                 {f(1, 6), f(1, 3), f(1, 3), f(1, 6)});
+      return true;
+    case MGRIT_ERK5:
+      rows_of<R>(t,
+                 {{zero},
+                  {f(1, 4)},
+                  {f(1, 8), f(1, 8)},
+                  {zero, zero, f(1, 2)},
+                  {f(3, 16), f(-3, 8), f(3, 8), f(9, 16)},
+                  {f(-3, 7), f(8, 7), f(6, 7), f(-12, 7), f(8, 7)}},
+                 {f(7, 90), zero, f(32, 90), f(12, 90), f(32, 90), f(7, 90)});
+      return true;
+    case MGRIT_SDIRK1:
+      rows_of<R>(t, {{one}}, {one});
+      return true;
+    case MGRIT_SDIRK2: {
+      const R r2 = Num<R>::sqrt2() / R(2);
+      rows_of<R>(t, {{one - r2}, {r2, one - r2}}, {r2, one - r2});
+      return true;
+    }
+    case MGRIT_SDIRK3: {
+      const R z = Num<R>::sdirk3_root();
+      const R be = (one - z) / R(2);
+      const R ga = f(-3, 2) * z * z + R(4) * z - f(1, 4);
+      const R ep = f(3, 2) * z * z - R(5) * z + f(5, 4);
+      rows_of<R>(t, {{z}, {be, z}, {ga, ep, z}}, {ga, ep, z});
+      return true;
+    }
+    case MGRIT_SDIRK4:
+      rows_of<R>(t,
+                 {{f(1, 4)},
+                  {f(1, 2), f(1, 4)},
+                  {f(17, 50), f(-1, 25), f(1, 4)},
+                  {f(371, 1360), f(-137, 2720), f(15, 544), f(1, 4)},
+                  {f(25, 24), f(-49, 48), f(125, 16), f(-85, 12), f(1, 4)}},
+                 {f(25, 24), f(-49, 48), f(125, 16), f(-85, 12), f(1, 4)});
+      return true;
+    default:
+      return false;
+  }
 }
 
 bool get_tableau(int scheme, Tableau& t) {
   t = Tableau();
-  const double r2 = std::sqrt(2.0) / 2.0;
-  switch (scheme) {
-    case MGRIT_ERK1:
-      set_rows(t, {{0.0}}, {1.0});
-      break;
-    case MGRIT_ERK2:
-      set_rows(t, {{0.0}, {1.0, 0.0}}, {0.5, 0.5});
-      break;
-    case MGRIT_ERK3:
-      set_rows(t, {{0.0}, {1.0}, {0.25, 0.25}}, {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0});
-      break;
-    case MGRIT_ERK4:
-      set_rows(t, {{0.0}, {0.5}, {0.0, 0.5}, {0.0, 0.0, 1.0}},
-               {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0});
-      break;
-    case MGRIT_ERK5:
-      set_rows(t,
-               {{0.0},
-                {0.25},
-                {0.125, 0.125},
-                {0.0, 0.0, 0.5},
-                {3.0 / 16.0, -3.0 / 8.0, 3.0 / 8.0, 9.0 / 16.0},
-                {-3.0 / 7.0, 8.0 / 7.0, 6.0 / 7.0, -12.0 / 7.0, 8.0 / 7.0}},
-               {7.0 / 90.0, 0.0, 32.0 / 90.0, 12.0 / 90.0, 32.0 / 90.0, 7.0 / 90.0});
-      break;
-    case MGRIT_SDIRK1:
-      set_rows(t, {{1.0}}, {1.0});
-      break;
-    case MGRIT_SDIRK2:
-      set_rows(t, {{1.0 - r2}, {r2, 1.0 - r2}}, {r2, 1.0 - r2});
-      break;
-    case MGRIT_SDIRK3: {
-      const double z = 0.43586652150845899942;
-      const double be = (1.0 - z) / 2.0;
-      const double ga = -1.5 * z * z + 4.0 * z - 0.25;
-      const double ep = 1.5 * z * z - 5.0 * z + 1.25;
-      set_rows(t, {{z}, {be, z}, {ga, ep, z}}, {ga, ep, z});
-      break;
-    }
-    case MGRIT_SDIRK4:
-      set_rows(t,
-               {{0.25},
-                {0.5, 0.25},
-                {17.0 / 50.0, -1.0 / 25.0, 0.25},
-                {371.0 / 1360.0, -137.0 / 2720.0, 15.0 / 544.0, 0.25},
-                {25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 0.25}},
-               {25.0 / 24.0, -49.0 / 48.0, 125.0 / 16.0, -85.0 / 12.0, 0.25});
-      break;
-    default:
-      return false;
+  TableauOf<double> x;
+  if (!tableau_of(scheme, x)) return false;
+  t.s = x.s;
+  for (int i = 0; i < x.s; ++i) {
+    for (int j = 0; j < x.s; ++j) t.A[i][j] = x.A[i][j];
+    t.b[i] = x.b[i];
   }
   t.implicit = scheme >= MGRIT_SDIRK1;
   t.p = t.implicit ? scheme - 10 : scheme;
   return true;
 }
 
-// Sec. 2.1: U1..U5.
+// Sec. 2.1: U1..U5 as fractions (offset, numerator, denominator).
+struct UpwindTerm {
+  int off;
+  int num, den;
+};
+static std::vector<UpwindTerm> upwind_terms(int p) {
+  switch (p) {
+    case 1: return {{0, 1, 1}, {-1, -1, 1}};
+    case 2: return {{0, 3, 2}, {-1, -4, 2}, {-2, 1, 2}};
+    case 3: return {{1, 2, 6}, {0, 3, 6}, {-1, -6, 6}, {-2, 1, 6}};
+    case 4: return {{1, 3, 12}, {0, 10, 12}, {-1, -18, 12}, {-2, 6, 12}, {-3, -1, 12}};
+    case 5:
+      return {{2, -3, 60}, {1, 30, 60}, {0, 20, 60}, {-1, -60, 60}, {-2, 15, 60},
+              {-3, -2, 60}};
+    default: return {};
+  }
+}
+
 void upwind(int p, std::vector<int>& off, std::vector<double>& d) {
   off.clear();
   d.clear();
-  auto add = [&](int o, double v) { off.push_back(o); d.push_back(v); };
-  switch (p) {
-    case 1: add(0, 1.0); add(-1, -1.0); break;
-    case 2: add(0, 1.5); add(-1, -2.0); add(-2, 0.5); break;
-    case 3:
-      add(1, 2.0 / 6.0); add(0, 3.0 / 6.0); add(-1, -1.0); add(-2, 1.0 / 6.0);
-      break;
-    case 4:
-      add(1, 3.0 / 12.0); add(0, 10.0 / 12.0); add(-1, -18.0 / 12.0);
-      add(-2, 6.0 / 12.0); add(-3, -1.0 / 12.0);
-      break;
-    case 5:
-      add(2, -3.0 / 60.0); add(1, 30.0 / 60.0); add(0, 20.0 / 60.0);
-      add(-1, -1.0); add(-2, 15.0 / 60.0); add(-3, -2.0 / 60.0);
-      break;
-    default: break;
+  for (const UpwindTerm& u : upwind_terms(p)) {
+    off.push_back(u.off);
+    d.push_back((double)u.num / (double)u.den);
   }
 }
 
@@ -182,49 +240,120 @@ double max_amplification(const Tableau& t, double cfl) {
 // ---------------------------------------------------------------------------
 // Corollary 1: the ERK stepper as one stencil
 // ---------------------------------------------------------------------------
+// The taps are the coefficients of R(Z) = sum_k g_k Z^k, Z = dt L a
+// polynomial of the shift, computed in binary128 from the tableau's
+// fractions so that rounding them to FP64 is the only error.  That rounding
+// is chosen (each tap within one unit in the last place of its value) to
+// keep the low Fourier modes of the stencil on the exact symbol: errors e_o
+// move the eigenvalue of mode theta by sum_o e_o exp(-i o theta) =
+// E0 - i theta E1 - theta^2/2 E2 + ..., E_q = sum_o o^q e_o (o the signed
+// offset), and n_t steps multiply that drift n_t-fold, so E0 (conservation
+// of the mean), E1 (transport speed) and E2 are driven toward zero.
+static void round_taps_preserving_moments(const std::map<int, quad>& exact, int nx,
+                                          Taps& out) {
+  const size_t n = exact.size();
+  std::vector<int> so;
+  std::vector<quad> ex;
+  std::vector<double> r;
+  std::vector<quad> ulp;
+  for (auto& a : exact) {
+    so.push_back(a.first > nx / 2 ? a.first - nx : a.first);
+    ex.push_back(a.second);
+    const double v = (double)a.second;
+    r.push_back(v);
+    ulp.push_back((quad)std::nextafter(std::fabs(v), HUGE_VAL) - (quad)std::fabs(v));
+  }
+  quad E[3] = {0, 0, 0};
+  for (size_t i = 0; i < n; ++i) {
+    const quad e = (quad)r[i] - ex[i], o = so[i];
+    E[0] += e;
+    E[1] += o * e;
+    E[2] += o * o * e;
+  }
+  // mode scale of the weights: theta ~ 0.05 (about 8 periods per 1000 points)
+  const quad w1 = quad(1) / quad(20), w2 = w1 * w1 / quad(2);
+  auto cost = [&](quad e0, quad e1, quad e2) {
+    const quad a = e0, b = w1 * e1, c = w2 * e2;
+    return a * a + b * b + c * c;
+  };
+  quad J = cost(E[0], E[1], E[2]);
+  for (int it = 0; it < 256; ++it) {
+    int bi = -1;
+    double bv = 0.0;
+    quad bJ = J;
+    for (size_t i = 0; i < n; ++i)
+      for (int dir = -1; dir <= 1; dir += 2) {
+        const double v = std::nextafter(r[i], dir > 0 ? HUGE_VAL : -HUGE_VAL);
+        quad dev = (quad)v - ex[i];
+        if (dev < 0) dev = -dev;
+        if (dev > ulp[i]) continue;
+        const quad d = (quad)v - (quad)r[i], o = so[i];
+        const quad j = cost(E[0] + d, E[1] + o * d, E[2] + o * o * d);
+        if (j < bJ) {
+          bJ = j;
+          bi = (int)i;
+          bv = v;
+        }
+      }
+    if (bi < 0) break;
+    const quad d = (quad)bv - (quad)r[bi], o = so[bi];
+    E[0] += d;
+    E[1] += o * d;
+    E[2] += o * o * d;
+    r[bi] = bv;
+    J = bJ;
+  }
+  out.off.clear();
+  out.w.clear();
+  size_t i = 0;
+  for (auto& a : exact) {
+    out.off.push_back(a.first);
+    out.w.push_back(r[i++]);
+  }
+}
+
 bool erk_taps(const Tableau& t, double cfl, int nx, Taps& out) {
   if (t.implicit) return false;
-  std::vector<int> off;
-  std::vector<double> d;
-  upwind(t.p, off, d);
+  TableauOf<quad> q;
+  const int scheme = t.p;  // ERKp has scheme id p
+  if (!tableau_of(scheme, q) || q.s != t.s) return false;
   // Z = dt L: (Z u)_i = -c sum_j d_j u_{i+j}; as first-column offset o = -j.
-  std::map<int, double> Z;
-  for (size_t j = 0; j < off.size(); ++j) Z[-off[j]] += -cfl * d[j];
+  std::map<int, quad> Z;
+  for (const UpwindTerm& u : upwind_terms(t.p))
+    Z[-u.off] += -(quad)cfl * (quad(u.num) / quad(u.den));
   // stability polynomial coefficients g_0 = 1, g_k = b^T A^{k-1} 1
-  double v[MAX_STAGES], nv[MAX_STAGES];
-  for (int i = 0; i < t.s; ++i) v[i] = 1.0;
-  std::vector<double> g(1, 1.0);
-  for (int k = 1; k <= t.s; ++k) {
-    double gk = 0.0;
-    for (int i = 0; i < t.s; ++i) gk += t.b[i] * v[i];
+  quad v[MAX_STAGES], nv[MAX_STAGES];
+  for (int i = 0; i < q.s; ++i) v[i] = 1;
+  std::vector<quad> g(1, quad(1));
+  for (int k = 1; k <= q.s; ++k) {
+    quad gk = 0;
+    for (int i = 0; i < q.s; ++i) gk += q.b[i] * v[i];
     g.push_back(gk);
-    for (int i = 0; i < t.s; ++i) {
-      nv[i] = 0.0;
-      for (int j = 0; j < t.s; ++j) nv[i] += t.A[i][j] * v[j];
+    for (int i = 0; i < q.s; ++i) {
+      nv[i] = 0;
+      for (int j = 0; j < q.s; ++j) nv[i] += q.A[i][j] * v[j];
     }
-    for (int i = 0; i < t.s; ++i) v[i] = nv[i];
+    for (int i = 0; i < q.s; ++i) v[i] = nv[i];
   }
-  std::map<int, double> phi, pw;  // pw = Z^k
-  pw[0] = 1.0;
+  std::map<int, quad> phi, pw;  // pw = Z^k
+  pw[0] = 1;
   phi[0] = g[0];
-  for (int k = 1; k <= t.s; ++k) {
-    std::map<int, double> nxt;
+  for (int k = 1; k <= q.s; ++k) {
+    std::map<int, quad> nxt;
     for (auto& a : pw)
       for (auto& b : Z) nxt[a.first + b.first] += a.second * b.second;
     pw.swap(nxt);
     for (auto& a : pw) phi[a.first] += g[k] * a.second;
   }
-  std::map<int, double> folded;
+  std::map<int, quad> folded;
   for (auto& a : phi) folded[((a.first % nx) + nx) % nx] += a.second;
-  double mx = 0.0;
-  for (auto& a : folded) mx = std::max(mx, std::fabs(a.second));
-  out.off.clear();
-  out.w.clear();
+  quad mx = 0;
+  for (auto& a : folded) mx = std::max(mx, a.second < 0 ? -a.second : a.second);
+  // coefficients that cancel exactly come out at the binary128 rounding level
+  std::map<int, quad> kept;
   for (auto& a : folded)
-    if (std::fabs(a.second) > 1e-13 * mx) {
-      out.off.push_back(a.first);
-      out.w.push_back(a.second);
-    }
+    if ((a.second < 0 ? -a.second : a.second) > quad(1e-24) * mx) kept.insert(a);
+  round_taps_preserving_moments(kept, nx, out);
   return true;
 }
 
@@ -758,52 +887,56 @@ void tap_window(const Taps& t, int nx, int& omin, int& W, std::vector<double>& d
 // ---------------------------------------------------------------------------
 // SDIRK stage matrix M = I - gamma dt L as cyclic recurrences
 // ---------------------------------------------------------------------------
-static std::vector<cd> poly_roots(const std::vector<double>& p) {
-  // p[q] = coefficient of s^q, degree D = p.size()-1; Durand-Kerner + Newton.
+using ld = long double;
+using cld = std::complex<long double>;
+
+// Roots of sum_q p[q] s^q (degree D = p.size()-1) in extended precision:
+// Durand-Kerner iterations, then Newton steps on each root.
+static std::vector<cld> poly_roots(const std::vector<ld>& p) {
   const int D = (int)p.size() - 1;
-  std::vector<cd> a(D + 1);
+  std::vector<cld> a(D + 1);
   for (int q = 0; q <= D; ++q) a[q] = p[q] / p[D];
-  auto ev = [&](cd z) {
-    cd r = a[D];
+  auto ev = [&](cld z) {
+    cld r = a[D];
     for (int q = D - 1; q >= 0; --q) r = r * z + a[q];
     return r;
   };
-  auto dev = [&](cd z) {
-    cd r = (double)D * a[D];
-    for (int q = D - 1; q >= 1; --q) r = r * z + (double)q * a[q];
+  auto dev = [&](cld z) {
+    cld r = (ld)D * a[D];
+    for (int q = D - 1; q >= 1; --q) r = r * z + (ld)q * a[q];
     return r;
   };
-  std::vector<cd> z(D);
-  cd seed(0.4, 0.9);
-  for (int i = 0; i < D; ++i) z[i] = std::pow(seed, i) * (1.0 + std::abs(a[0]));
-  for (int it = 0; it < 1000; ++it) {
-    double delta = 0.0;
+  std::vector<cld> z(D);
+  const cld seed(0.4L, 0.9L);
+  for (int i = 0; i < D; ++i) z[i] = std::pow(seed, i) * (1.0L + std::abs(a[0]));
+  for (int it = 0; it < 2000; ++it) {
+    ld delta = 0.0L;
     for (int i = 0; i < D; ++i) {
-      cd den = 1.0;
+      cld den = 1.0L;
       for (int j = 0; j < D; ++j)
         if (j != i) den *= (z[i] - z[j]);
-      cd dz = ev(z[i]) / den;
+      const cld dz = ev(z[i]) / den;
       z[i] -= dz;
       delta = std::max(delta, std::abs(dz));
     }
-    if (delta < 1e-16) break;
+    if (delta < 1e-19L) break;
   }
   for (int i = 0; i < D; ++i)
     for (int it = 0; it < 3; ++it) {
-      cd d = dev(z[i]);
+      const cld d = dev(z[i]);
       if (std::abs(d) > 0) z[i] -= ev(z[i]) / d;
     }
   return z;
 }
 
-static void mat2_mul(const double* a, const double* b, double* c) {
-  double r[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
-                 a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
+static void mat2_mul(const ld* a, const ld* b, ld* c) {
+  ld r[4] = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3],
+             a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
   for (int i = 0; i < 4; ++i) c[i] = r[i];
 }
 
-static void mat2_pow(const double* a, long long e, double* out) {
-  double r[4] = {1, 0, 0, 1}, b[4] = {a[0], a[1], a[2], a[3]};
+static void mat2_pow(const ld* a, long long e, ld* out) {
+  ld r[4] = {1, 0, 0, 1}, b[4] = {a[0], a[1], a[2], a[3]};
   while (e > 0) {
     if (e & 1) mat2_mul(r, b, r);
     mat2_mul(b, b, b);
@@ -812,6 +945,16 @@ static void mat2_pow(const double* a, long long e, double* out) {
   for (int i = 0; i < 4; ++i) out[i] = r[i];
 }
 
+// The stage matrix M = I - gamma dt L = K prod_f (1 - a1_f X - a2_f X^2)
+// (X the shift S or S^{-1}) is applied as M^{-1} = scale prod_f (factor
+// f)^{-1}.  Roots, factors and the scan constants are computed in extended
+// precision and rounded to FP64 once.  On the constant mode (theta = 0) the
+// exact M is 1 (the upwind weights sum to zero), and any error of the
+// rounded M^{-1} there is repeated every stage of every step: the mean
+// drifts n_t-fold.  So the FP64 factor coefficients are taken within a few
+// units in the last place of their values such that scale, the FP64 value
+// nearest to prod_f (1 - a1_f - a2_f), reproduces that product most
+// closely.
 bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
                  std::string& err) {
   out = SdirkDev();
@@ -825,140 +968,218 @@ bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
       err = "tableau is not singly diagonal";
       return false;
     }
-  std::vector<int> off;
-  std::vector<double> d;
-  upwind(t.p, off, d);
+  TableauOf<ld> tl;
+  if (!tableau_of(t.p + 10, tl)) {
+    err = "unknown SDIRK scheme";
+    return false;
+  }
+  const ld gl = tl.A[0][0];
   // (M u)_i = sum_j coef_j u_{i+j};  M = I + gamma c D.
-  std::map<int, double> coef;
-  for (size_t j = 0; j < off.size(); ++j) coef[off[j]] += g * cfl * d[j];
-  coef[0] += 1.0;
+  std::map<int, ld> coef;
+  for (const UpwindTerm& u : upwind_terms(t.p))
+    coef[u.off] += gl * (ld)cfl * ((ld)u.num / (ld)u.den);
+  coef[0] += 1.0L;
   const int jmin = coef.begin()->first, jmax = coef.rbegin()->first;
   const int D = jmax - jmin;
   // S^{jmax} M = P(S), P(s) = sum_j coef_j s^{jmax - j}, S u_i = u_{i-1}
-  std::vector<double> p(D + 1, 0.0);
+  std::vector<ld> p(D + 1, 0.0L);
   for (auto& c : coef) p[jmax - c.first] = c.second;
-  std::vector<cd> r = poly_roots(p);
-  std::vector<cd> outside, inside;
+  std::vector<cld> r = poly_roots(p);
+  std::vector<cld> outside, inside;
   for (auto& z : r) {
-    if (std::fabs(std::abs(z) - 1.0) < 1e-10) {
+    if (std::fabs(std::abs(z) - 1.0L) < 1e-10L) {
       err = "stage matrix has a root on the unit circle";
       return false;
     }
-    (std::abs(z) > 1.0 ? outside : inside).push_back(z);
+    (std::abs(z) > 1.0L ? outside : inside).push_back(z);
   }
   if ((int)inside.size() != jmax) {
     err = "unexpected root split of the stage matrix";
     return false;
   }
-  cd Kc = coef.begin()->second;
-  for (auto& z : outside) Kc *= -z;
-  // group roots into factors of order <= 2 with real coefficients
-  auto make_factors = [&](std::vector<cd> roots, int dir) {
-    std::vector<RecDev> fs;
+  // factors of order <= 2 with real coefficients, in extended precision
+  struct Fac {
+    int dir;
+    ld a1, a2;
+  };
+  auto make_factors = [&](std::vector<cld> roots, int dir) {
+    std::vector<Fac> fs;
     std::vector<bool> used(roots.size(), false);
-    std::vector<cd> reals;
+    std::vector<ld> reals;
     for (size_t i = 0; i < roots.size(); ++i) {
       if (used[i]) continue;
-      if (std::fabs(roots[i].imag()) > 1e-12 * std::abs(roots[i])) {
+      if (std::fabs(roots[i].imag()) > 1e-12L * std::abs(roots[i])) {
         size_t best = i;
-        double bd = 1e300;
+        ld bd = 1e300L;
         for (size_t j = 0; j < roots.size(); ++j)
           if (j != i && !used[j]) {
-            double dd = std::abs(roots[j] - std::conj(roots[i]));
-            if (dd < bd) { bd = dd; best = j; }
+            const ld dd = std::abs(roots[j] - std::conj(roots[i]));
+            if (dd < bd) {
+              bd = dd;
+              best = j;
+            }
           }
         used[i] = used[best] = true;
-        RecDev f = {};
-        f.dir = dir;
-        cd q1 = dir > 0 ? 1.0 / roots[i] : roots[i];
-        cd q2 = dir > 0 ? 1.0 / roots[best] : roots[best];
-        f.a1 = (q1 + q2).real();
-        f.a2 = -(q1 * q2).real();
-        fs.push_back(f);
+        const cld q1 = dir > 0 ? 1.0L / roots[i] : roots[i];
+        const cld q2 = dir > 0 ? 1.0L / roots[best] : roots[best];
+        fs.push_back({dir, (q1 + q2).real(), -(q1 * q2).real()});
       } else {
         used[i] = true;
-        reals.push_back(roots[i]);
+        reals.push_back(roots[i].real());
       }
     }
     for (size_t i = 0; i < reals.size(); i += 2) {
-      RecDev f = {};
-      f.dir = dir;
-      double q1 = dir > 0 ? 1.0 / reals[i].real() : reals[i].real();
+      const ld q1 = dir > 0 ? 1.0L / reals[i] : reals[i];
       if (i + 1 < reals.size()) {
-        double q2 = dir > 0 ? 1.0 / reals[i + 1].real() : reals[i + 1].real();
-        f.a1 = q1 + q2;
-        f.a2 = -q1 * q2;
+        const ld q2 = dir > 0 ? 1.0L / reals[i + 1] : reals[i + 1];
+        fs.push_back({dir, q1 + q2, -q1 * q2});
       } else {
-        f.a1 = q1;
-        f.a2 = 0.0;
+        fs.push_back({dir, q1, 0.0L});
       }
-      fs.push_back(f);
     }
     return fs;
   };
-  std::vector<RecDev> fs = make_factors(outside, +1);
-  std::vector<RecDev> fb = make_factors(inside, -1);
-  fs.insert(fs.end(), fb.begin(), fb.end());
-  if ((int)fs.size() > MAX_FACTORS) {
+  std::vector<Fac> fx = make_factors(outside, +1);
+  {
+    std::vector<Fac> fb = make_factors(inside, -1);
+    fx.insert(fx.end(), fb.begin(), fb.end());
+  }
+  const int nf = (int)fx.size();
+  if (nf > MAX_FACTORS) {
     err = "too many recurrence factors";
     return false;
   }
-  // check: K * prod_f (1 - a1 X - a2 X^2) (X = S or S^{-1}) reproduces M
+  // FP64 coefficients: nearest values, then up to three non-zero ones (those
+  // with the finest spacing) moved by at most kReach units in the last place
+  // where that brings scale * prod_f (factor f)^{-1}, with scale the FP64
+  // value nearest to prod_f (1 - a1_f - a2_f), closest to the exact M^{-1}
+  // on the constant mode and a few long waves (theta <= 0.05)
+  std::vector<double> c64(2 * nf);
+  for (int q = 0; q < nf; ++q) {
+    c64[2 * q] = (double)fx[q].a1;
+    c64[2 * q + 1] = (double)fx[q].a2;
+  }
+  auto prod_at_one = [&](const std::vector<double>& c) {
+    ld pr = 1.0L;
+    for (int q = 0; q < nf; ++q) pr *= 1.0L - (ld)c[2 * q] - (ld)c[2 * q + 1];
+    return pr;
+  };
+  const ld kTheta[4] = {0.0L, 0.0125L, 0.025L, 0.05L};
+  cld Mex[4];
+  for (int k = 0; k < 4; ++k) {
+    cld m = 0.0L;
+    for (auto& c : coef) m += c.second * std::exp(cld(0.0L, (ld)c.first * kTheta[k]));
+    Mex[k] = m;  // symbol of M: (M e)_i = sum_j coef_j e_{i+j}
+  }
+  auto mismatch = [&](const std::vector<double>& c) {
+    const ld sc = (ld)(double)prod_at_one(c);
+    ld worst = 0.0L;
+    for (int k = 0; k < 4; ++k) {
+      cld den = 1.0L;
+      for (int q = 0; q < nf; ++q) {
+        // S e_i = e_{i-1}: X = e^{-i theta} forward, e^{+i theta} backward
+        const cld X = std::exp(cld(0.0L, fx[q].dir > 0 ? -kTheta[k] : kTheta[k]));
+        den *= 1.0L - (ld)c[2 * q] * X - (ld)c[2 * q + 1] * X * X;
+      }
+      worst = std::max(worst, std::abs(sc / den * Mex[k] - 1.0L));
+    }
+    return worst;
+  };
   {
-    std::map<int, double> prod;
-    prod[0] = Kc.real();
-    for (auto& f : fs) {
-      std::map<int, double> nxt;
+    std::vector<int> idx;
+    for (int i = 0; i < 2 * nf; ++i)
+      if (c64[i] != 0.0) idx.push_back(i);
+    std::sort(idx.begin(), idx.end(),
+              [&](int x, int y) { return std::fabs(c64[x]) < std::fabs(c64[y]); });
+    if (idx.size() > 3) idx.resize(3);
+    constexpr int kReach = 6;
+    auto shifted = [](double v, int k) {
+      for (; k > 0; --k) v = std::nextafter(v, HUGE_VAL);
+      for (; k < 0; ++k) v = std::nextafter(v, -HUGE_VAL);
+      return v;
+    };
+    int r[3] = {0, 0, 0};
+    for (size_t i = 0; i < idx.size(); ++i) r[i] = kReach;
+    std::vector<double> best = c64;
+    ld bm = mismatch(c64);
+    for (int k0 = -r[0]; k0 <= r[0]; ++k0)
+      for (int k1 = -r[1]; k1 <= r[1]; ++k1)
+        for (int k2 = -r[2]; k2 <= r[2]; ++k2) {
+          std::vector<double> c = c64;
+          const int ks[3] = {k0, k1, k2};
+          for (size_t i = 0; i < idx.size(); ++i) c[idx[i]] = shifted(c64[idx[i]], ks[i]);
+          const ld mm = mismatch(c);
+          if (mm < bm) {
+            bm = mm;
+            best = c;
+          }
+        }
+    c64 = best;
+  }
+  // check: K * prod_f (1 - a1 X - a2 X^2) (X = S or S^{-1}) reproduces M
+  const ld Kc = 1.0L / prod_at_one(c64);
+  {
+    std::map<int, ld> prod;
+    prod[0] = Kc;
+    for (int q = 0; q < nf; ++q) {
+      std::map<int, ld> nxt;
       // factor as Laurent polynomial in S: dir +1 -> powers 0, 1, 2 of S
       // (first-column offsets 0, 1, 2); dir -1 -> offsets 0, -1, -2
-      int s1 = f.dir > 0 ? 1 : -1;
+      const int s1 = fx[q].dir > 0 ? 1 : -1;
       for (auto& a : prod) {
         nxt[a.first] += a.second;
-        nxt[a.first + s1] += -f.a1 * a.second;
-        nxt[a.first + 2 * s1] += -f.a2 * a.second;
+        nxt[a.first + s1] += -(ld)c64[2 * q] * a.second;
+        nxt[a.first + 2 * s1] += -(ld)c64[2 * q + 1] * a.second;
       }
       prod.swap(nxt);
     }
-    double mx = 0.0;
+    ld mx = 0.0L;
     for (auto& c : coef) mx = std::max(mx, std::fabs(c.second));
-    std::map<int, double> want;  // first-column offsets of M: o = -j
+    std::map<int, ld> want;  // first-column offsets of M: o = -j
     for (auto& c : coef) want[-c.first] = c.second;
     for (auto& a : prod) {
-      double w = want.count(a.first) ? want[a.first] : 0.0;
-      if (std::fabs(a.second - w) > 1e-12 * mx) {
+      const ld w = want.count(a.first) ? want[a.first] : 0.0L;
+      if (std::fabs(a.second - w) > 1e-12L * mx) {
         err = "stage-matrix factorization check failed";
         return false;
       }
     }
   }
   out.s = t.s;
-  out.nf = (int)fs.size();
+  out.nf = nf;
   out.K = K;
   out.NL = NL;
   for (int i = 0; i < t.s; ++i) {
     for (int j = 0; j < t.s; ++j) out.A[i][j] = t.A[i][j];
     out.b[i] = t.b[i];
   }
-  out.inv_gamma = 1.0 / g;
-  out.scale = 1.0 / Kc.real();
-  for (int q = 0; q < out.nf; ++q) {
-    RecDev f = fs[q];
-    double C[4] = {f.a1, f.a2, 1.0, 0.0};
-    double H[4];
+  out.inv_gamma = (double)(1.0L / gl);
+  out.scale = (double)prod_at_one(c64);
+  for (int q = 0; q < nf; ++q) {
+    RecDev f = {};
+    f.dir = fx[q].dir;
+    f.a1 = c64[2 * q];
+    f.a2 = c64[2 * q + 1];
+    const ld C[4] = {(ld)f.a1, (ld)f.a2, 1.0L, 0.0L};
+    ld H[4];
     mat2_pow(C, K, H);
-    for (int dd = 0; dd < 11; ++dd) mat2_pow(H, 1LL << dd, f.Hp[dd]);
-    double HN[4];
+    for (int dd = 0; dd < 11; ++dd) {
+      ld Hd[4];
+      mat2_pow(H, 1LL << dd, Hd);
+      for (int i = 0; i < 4; ++i) f.Hp[dd][i] = (double)Hd[i];
+    }
+    ld HN[4];
     mat2_pow(H, NL, HN);
-    double a = 1.0 - HN[0], b = -HN[1], c = -HN[2], e = 1.0 - HN[3];
-    double det = a * e - b * c;
-    if (!(std::fabs(det) > 1e-300)) {
+    const ld a = 1.0L - HN[0], b = -HN[1], c = -HN[2], e = 1.0L - HN[3];
+    const ld det = a * e - b * c;
+    if (!(std::fabs(det) > 1e-300L)) {
       err = "singular cyclic closure";
       return false;
     }
-    f.Cinv[0] = e / det;
-    f.Cinv[1] = -b / det;
-    f.Cinv[2] = -c / det;
-    f.Cinv[3] = a / det;
+    f.Cinv[0] = (double)(e / det);
+    f.Cinv[1] = (double)(-b / det);
+    f.Cinv[2] = (double)(-c / det);
+    f.Cinv[3] = (double)(a / det);
     out.f[q] = f;
   }
   return true;

@@ -134,6 +134,13 @@ def _check_hist(g, R):
     ("SDIRK4", 128, 256, 8, 2, "V", None),
     ("ERK3", 100, 400, 4, 3, "V", None),       # ragged n_x: generic kernel
     ("ERK2", 192, 768, 4, 3, "F", None),
+    ("ERK4", 256, 1024, 4, 3, "V", None),       # Table 7's ERK4 with U4
+    ("ERK4", 128, 2048, 8, 3, "F", None),
+    ("SDIRK1", 128, 256, 8, 2, "V", None),      # each SDIRK order at a second m
+    ("SDIRK2", 128, 512, 16, 2, "V", None),
+    ("SDIRK3", 128, 512, 4, 2, "V", None),
+    ("SDIRK3", 128, 512, 8, 3, "V", None),      # SDIRK on three levels
+    ("SDIRK4", 128, 512, 4, 2, "V", None),
 ])
 def test_mgrit_counts_and_history(scheme, nx, nt, m, levels, cycle, widths):
     d, R, g, _ = _compare(scheme, nx, nt, m, levels, cycle=cycle, widths=widths)
