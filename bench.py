@@ -5,23 +5,37 @@
 A step is one whole solve: FCF-MGRIT from the seeded U[0,1) initial
 iterate to a space-time residual <= 1e-10 (discrete L2 norm), every level
 of the hierarchy, with u0 and the initial iterate already resident in HBM.
-The default workload is ERK3+U3, n_x = 4096, n_t = 16384, m = 8, 4-level
-F-cycles, FP64.  value = n_x * n_t / (seconds per solve) in fine-step DOF/s.
+The default workload is the largest single-GPU configuration and the one
+the precision comparison is quoted on: ERK5+U5, n_x = 8192, n_t = 65536,
+m = 8, 5-level V-cycles, FP32 relaxation of FP64 iterates (residual of the
+relaxed iterate, coarse levels and norms in FP64); value = n_x * n_t /
+(seconds per solve) in fine-step DOF/s.  The same solve in plain FP64 is
+timed next to it over the same number of steps.
 
 The JSON line also carries:
   roofline      the fine-level relaxation kernel (the dominant one): its
-                algorithmic HBM bytes per launch divided by its mean launch
-                time from HIP events recorded on the plan's stream;
+                algorithmic work per launch (flops for VALU-bound stencils,
+                HBM bytes for bandwidth-bound ones) divided by its mean
+                launch time from HIP events recorded on the plan's stream;
+  by_pass       every (level, pass, precision) of one profiled solve with its
+                time per solve and its achieved HBM bandwidth and flop rate
+                from the library's algorithmic byte and flop counts;
+  error         the relative error of the returned C-points against a plain
+                FP64 solve to 1e-14 of the same workload (which the GPU tests
+                hold within 1e-12 of the oracle's exact discrete solution);
   cpu_baseline  the CPU oracle's sequential time-stepping (the plain
                 definition of the result), timed on a bounded sample of the
                 same workload on the host;
-  workloads     the other solver forms (the 64 x 256 ERK1, the SDIRK3 and
-                the ERK5 FP32-relaxation/FP64 pair), with time to tolerance;
+  workloads     the other configurations (ERK3 F-cycles, SDIRK3, the 64 x 256
+                ERK1 check, inflow boundaries, the Sec. 4.4 width rule), each
+                timed over at least 5 solves with its own roofline and error;
   gpu_sequential  sequential time-stepping on the GPU (one workgroup,
-                n_t steps) and MGRIT's speed-up over it.
+                n_t steps) and MGRIT's speed-up over it;
+  serving       the request mix of the serving form (p50/p99 latency).
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,9 +49,14 @@ sys.path.insert(0, ROOT)
 METRIC = ("time to ‖r‖≤1e-10 & fine-step DOF/s (FP32-relax vs FP64); "
           "serve p50/p99")
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFS = 78.6
-MAIN = "erk3_u3_nx4096_nt16384_m8_fcycle"
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (one FMA per lane
+# per clock) x 2.4 GHz.  Non-packed FP32 FMAs issue at the same rate (the
+# 157.3 TFLOP/s FP32 figure needs packed FP32, which this build disables),
+# so FP32 passes are priced against the same peak.
+VALU_PEAK_TFS = 78.6
+MAIN = "erk5_u5_nx8192_nt65536_m8_fp32relax"
 TOL = 1e-10
+REF_TOL = 1e-14
 
 
 def _plan(w, precision=None):
@@ -59,39 +78,52 @@ def _inputs(w, torch):
     return u0, uinit
 
 
-def _timed_solves(P, u0, uinit, steps, warmup, torch, each=None):
-    """Mean seconds per solve over `steps` timed solves (after `warmup`);
-    each solve returns only once its GPU work is done, so `each` (a list)
-    receives the per-solve times too."""
+def _timed_solves(P, u0, uinit, steps, warmup, torch):
+    """(mean seconds per solve, per-solve seconds, last result) over `steps`
+    timed solves after `warmup`; every solve returns once its GPU work is
+    done, and the whole timed region is bracketed by synchronisations."""
     out = torch.empty((1, P.nx), dtype=torch.float64, device="cuda")
     res = None
     for _ in range(warmup):
         res = P.solve(u0, uinit, tol=TOL, maxit=100, out="final", u_out=out)
     torch.cuda.synchronize()
+    each = []
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
         res = P.solve(u0, uinit, tol=TOL, maxit=100, out="final", u_out=out)
-        if each is not None:
-            each.append(time.perf_counter() - t1)
+        each.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(steps, 1)
-    return dt, res
+    return dt, each, res
 
 
-def _fine_nnz(w):
-    from paper_1910_03726_amd import mgrit as M
-    if w["scheme"].startswith("SDIRK"):
-        return None
-    off, _ = M.phi_taps(w["scheme"], w["cfl"], w["nx"])
-    return len(off)
+def _stats_ms(each):
+    a = 1e3 * np.asarray(each)
+    return {"median": round(float(np.median(a)), 4), "p95": round(float(np.percentile(a, 95)), 4),
+            "min": round(float(a.min()), 4), "n": int(a.size)}
 
 
-def measured_traffic(workload, source="relax_kernels.h"):
+def _cpoint_error(P, u0, uinit, ref, torch):
+    """Max relative error of the C-points of a solve to TOL against `ref`
+    (C-points of the FP64 solve to REF_TOL), on the device."""
+    r = P.solve(u0, uinit, tol=TOL, maxit=100, out="cpoints")
+    err = float((r.out - ref).abs().max() / ref.abs().max())
+    return err
+
+
+def _reference(w, u0, uinit, torch):
+    """C-points of the plain FP64 solve of the same workload to REF_TOL."""
+    P, _ = _plan(w, "fp64")
+    r = P.solve(u0, uinit, tol=REF_TOL, maxit=100, out="cpoints")
+    P.close()
+    return r.out, r.hist[-1]
+
+
+def measured_traffic(workload, source):
     """HBM bytes per launch of the fine relaxation kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
     changed since the counters were taken (hash recorded in the summary)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")
     src = os.path.join(ROOT, "paper_1910_03726_amd", "csrc", source)
     if not os.path.exists(path):
@@ -106,48 +138,62 @@ def measured_traffic(workload, source="relax_kernels.h"):
     return val if rec == sha else None
 
 
-def roofline(P, w, u0, uinit, torch, workload):
-    """Fine relaxation kernel: algorithmic bytes and flops over its launches."""
+def _kernel_source(w):
+    if w.get("boundary") == "inflow":
+        return "bounded_kernels.h", "k_bounded_tiled"
+    if w["scheme"].startswith("SDIRK"):
+        return "sdirk_kernels.h", "k_sdirk"
+    return "relax_kernels.h", "k_stencil"
+
+
+def profiled(P, u0, uinit):
+    """One profiled solve: the per-class split and the (level, pass,
+    precision) table with achieved rates from algorithmic bytes and flops."""
     P.set_profiling(True)
     r = P.solve(u0, uinit, tol=TOL, maxit=100, out="none")
     prof = P.profile()
+    detail = P.profile_detail()
     P.set_profiling(False)
-    nx, m = w["nx"], w["m"]
-    inflow = w.get("boundary") == "inflow"
-    nc = w["nt"] // m
-    it = r.iters
-    # FC passes read the start C-point (and the correction after the first
-    # iteration) and write one C-point; residual passes read two C-points and
-    # write one: 8 bytes each, per interval and point.
-    arrays = (2 + 3 * it) + 3 * (it + 1)
-    launches = prof["launches"]["relax_fine"]
-    bytes_total = arrays * nc * nx * 8.0
-    ms = prof["ms"]["relax_fine"]
-    avg_ms = ms / max(launches, 1)
-    nnz = _fine_nnz(w)
-    flops_total = 2.0 * nnz * prof["fine_dof_steps"] if nnz else None
-    achieved_gbs = bytes_total / launches / (avg_ms * 1e-3) / 1e9
-    t_hbm = bytes_total / (HBM_PEAK_GBS * 1e9)
-    t_alu = flops_total / (FP64_PEAK_TFS * 1e12) if flops_total else 0.0
-    out = {"bound": "hbm" if t_hbm >= t_alu else "alu",
-           "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-           "traffic": measured_traffic(workload, "bounded_kernels.h" if inflow else
-                                       "relax_kernels.h"),
-           "kernel": ("k_bounded_tiled" if inflow else "k_stencil") +
-                     " (fine-level FC and residual passes)",
-           "launches": launches, "avg_launch_ms": round(avg_ms, 5),
-           "bytes_per_launch": bytes_total / launches,
-           "fp64_tflops_achieved": (round(flops_total / (ms * 1e-3) / 1e12, 2)
-                                    if flops_total else None),
-           "fp64_tflops_peak": FP64_PEAK_TFS,
-           "relaxation_dof_steps_per_s": prof["fine_dof_steps"] / (ms * 1e-3),
-           "ms_by_class": {k: round(v, 4) for k, v in prof["ms"].items()},
-           "launches_by_class": prof["launches"]}
-    if out["bound"] == "alu":
-        a = flops_total / launches / (avg_ms * 1e-3) / 1e12
-        out.update({"achieved": round(a, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                    "frac": round(a / FP64_PEAK_TFS, 4)})
+    rows = []
+    for e in detail:
+        s = e["ms"] * 1e-3
+        gbs = e["bytes"] / s / 1e9 if s > 0 else 0.0
+        tfs = e["flops"] / s / 1e12 if s > 0 else 0.0
+        rows.append({"level": e["level"] + 1, "pass": e["pass"], "precision": e["precision"],
+                     "launches": e["launches"], "ms": round(e["ms"], 4),
+                     "avg_us": round(1e3 * e["ms"] / max(e["launches"], 1), 2),
+                     "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "TFLOP/s": round(tfs, 2), "valu_frac": round(tfs / VALU_PEAK_TFS, 4)})
+    return r, prof, detail, rows
+
+
+def roofline(w, detail, workload):
+    """The fine relaxation passes (level 1, passes fc and res, both
+    precisions): algorithmic work per launch over the mean launch time.
+    The bound is the resource whose peak the algorithmic work would take
+    longer to saturate."""
+    fine = [e for e in detail if e["level"] == 0 and e["pass"] in ("fc", "res")]
+    launches = sum(e["launches"] for e in fine)
+    ms = sum(e["ms"] for e in fine)
+    by = sum(e["bytes"] for e in fine)
+    fl = sum(e["flops"] for e in fine)
+    src, kname = _kernel_source(w)
+    avg_s = ms * 1e-3 / max(launches, 1)
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    t_alu = fl / (VALU_PEAK_TFS * 1e12)
+    gbs = by / launches / avg_s / 1e9
+    tfs = fl / launches / avg_s / 1e12
+    out = {"kernel": kname + " (fine-level FC and residual passes)",
+           "launches": launches, "avg_launch_ms": round(avg_s * 1e3, 5),
+           "bytes_per_launch": by / launches, "flops_per_launch": fl / launches,
+           "hbm_gbs": round(gbs, 1), "valu_tflops": round(tfs, 2),
+           "traffic": measured_traffic(workload, src)}
+    if t_hbm >= t_alu:
+        out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    else:
+        out.update({"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": round(tfs / VALU_PEAK_TFS, 4)})
     return out
 
 
@@ -164,9 +210,12 @@ def cpu_baseline(w, seconds=10.0):
     t0 = time.perf_counter()
     d.propagate(u, n)
     t = time.perf_counter() - t0
+    cpus = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": w["nx"] * n / t, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "host_cpus": cpus,
             "sample": f"{n} of the {w['nt']} sequential time steps of the oracle "
-                      f"(numpy, staged {w['scheme']}), n_x = {w['nx']}, {t:.1f} s"}
+                      f"(numpy, staged {w['scheme']}, one thread), n_x = {w['nx']}, "
+                      f"{t:.1f} s"}
 
 
 def gpu_sequential(P, w, u0, torch):
@@ -216,7 +265,6 @@ def _serve_run(reqs, u0s, arrivals, slots, setup_threads, budget):
 def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
     """The serving mix: saturated throughput, then Poisson arrivals at 80% of
     it (p50/p99 latency); the plain FP64 per-solve form on a 10% sample."""
-    import numpy as np
     from paper_1910_03726_amd import inputs, mgrit as M
     reqs = inputs.serving_requests(n, seed=7)
     u0s = [inputs.request_u0(q) for q in reqs]
@@ -246,7 +294,8 @@ def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
             "hbm_peak_gib": round(st.hbm_peak / (1 << 30), 3),
             "psi_cache_hits": st.psi_cache_hits, "psi_cache_misses": st.psi_cache_misses,
             "batches": st.batches, "batched_requests": st.batched_requests,
-            "saturated": {"makespan_s": round(span, 3), "requests_per_s": round(rate, 2),
+            "saturated": {"note": "all requests submitted at t = 0: latency is queueing",
+                          "makespan_s": round(span, 3), "requests_per_s": round(rate, 2),
                           "dof_per_s": dof / span,
                           "p50_ms": round(float(np.percentile(lat_sat, 50)), 3),
                           "p99_ms": round(float(np.percentile(lat_sat, 99)), 3)},
@@ -262,60 +311,42 @@ def serving(n, torch, slots=8, setup_threads=8, budget_gib=128):
             "serving_speedup_vs_per_solve": round((dof / span) / (sdof / tb), 2)}
 
 
-def _auto_levels(nt, m):
-    L, span = 2, m * m
-    while nt % span == 0 and nt // span >= 8:
-        L += 1
-        span *= m
-    return L
-
-
-def workload_line(name, steps, warmup, torch, precision=None, psi_rule=None):
-    from paper_1910_03726_amd import inputs
-    w = dict(inputs.WORKLOADS[name])
-    if psi_rule:
-        w["psi_rule"] = psi_rule
+def solve_record(name, w, steps, warmup, torch, precision=None, ref=None):
+    """Time `steps` solves of workload w (after `warmup`), profile one, and
+    measure the error of its C-points against the FP64 reference."""
     P, psi = _plan(w, precision)
     u0, uinit = _inputs(w, torch)
-    dt, r = _timed_solves(P, u0, uinit, steps, warmup, torch)
+    dt, each, r = _timed_solves(P, u0, uinit, steps, warmup, torch)
     st = r.stats
-    d = {"precision": precision or w["precision"], "psi_rule": w["psi_rule"],
-         "ms_to_tol": round(dt * 1e3, 3),
-         "dof_per_s": w["nx"] * w["nt"] / dt, "iterations": r.iters,
-         "outer_iterations": st.outer_iterations, "final_residual": r.hist[-1],
-         "fine_passes_fp64": st.fine_passes_fp64, "fine_passes_fp32": st.fine_passes_fp32,
-         "psi_nnz": [len(o) for o, _ in psi], "kernels": P.describe()}
+    rec = {"precision": precision or w["precision"], "psi_rule": w["psi_rule"],
+           "ms_to_tol": round(dt * 1e3, 4), "step_ms": _stats_ms(each),
+           "dof_per_s": w["nx"] * w["nt"] / dt, "iterations": r.iters,
+           "outer_iterations": st.outer_iterations, "final_residual": r.hist[-1],
+           "fine_passes_fp64": st.fine_passes_fp64, "fine_passes_fp32": st.fine_passes_fp32,
+           "psi_nnz": [len(o) for o, _ in psi], "kernels": P.describe()}
     oc = P.operator_complexity()
     if oc == oc:
-        d["operator_complexity"] = round(oc, 4)
-    # fine relaxation passes of one profiled solve (HIP events per launch):
-    # ERK passes do 2 nnz(Phi) flops per fine DOF-step; FP32 passes run at
-    # the FP64 vector rate (packed FP32 is not used), so both are priced
-    # against the FP64 vector peak
-    P.set_profiling(True)
-    P.solve(u0, uinit, tol=TOL, maxit=100, out="none")
-    prof = P.profile()
-    P.set_profiling(False)
-    nnz = _fine_nnz(w)
-    ms, n = prof["ms"]["relax_fine"], prof["launches"]["relax_fine"]
-    fp = {"launches": n, "avg_ms": round(ms / max(n, 1), 4)}
-    if nnz and ms > 0:
-        tf = 2.0 * nnz * prof["fine_dof_steps"] / (ms * 1e-3) / 1e12
-        fp.update({"tflops": round(tf, 2), "frac_of_fp64_vector_peak": round(tf / FP64_PEAK_TFS, 4)})
-    d["fine_pass"] = fp
-    d["ms_by_class"] = {k: round(v, 4) for k, v in prof["ms"].items()}
-    P.close()
-    return d
+        rec["operator_complexity"] = round(oc, 4)
+    _, prof, detail, rows = profiled(P, u0, uinit)
+    rec["roofline"] = roofline(w, detail, name)
+    rec["ms_by_class"] = {k: round(v, 4) for k, v in prof["ms"].items()}
+    rec["by_pass"] = rows
+    if ref is None:
+        ref, rres = _reference(w, u0, uinit, torch)
+        rec["reference_residual"] = rres
+    rec["error_vs_fp64_reference"] = _cpoint_error(P, u0, uinit, ref, torch)
+    return P, u0, uinit, rec, ref, dt, each
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=MAIN)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline solve (for profiler runs)")
     ap.add_argument("--serve", type=int, default=2000, metavar="N",
                     help="requests in the serving measurement (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -339,12 +370,19 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    P, psi = _plan(w)
-    u0, uinit = _inputs(w, torch)
-    each = []
-    dt, r = _timed_solves(P, u0, uinit, a.steps, a.warmup, torch, each)
+    if a.no_extra:
+        P, psi = _plan(w)
+        u0, uinit = _inputs(w, torch)
+        dt, each, r = _timed_solves(P, u0, uinit, a.steps, a.warmup, torch)
+        print(json.dumps({"workload": a.workload, "ms_per_step": round(dt * 1e3, 4),
+                          "iterations": r.iters, "final_residual": r.hist[-1],
+                          "kernels": P.describe()}), flush=True)
+        P.close()
+        return
+    steps = max(a.steps, 1)
+    P, u0, uinit, rec, ref, dt, each = solve_record(a.workload, w, steps, a.warmup, torch)
     line = {"metric": METRIC, "value": w["nx"] * w["nt"] / dt, "unit": "DOF/s",
-            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "n_gpus": 1, "steps": steps, "warmup": a.warmup,
             "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if w["precision"] == "fp64" else "f32+f64",
@@ -352,34 +390,53 @@ def main():
             "config": {"workload": a.workload, "scheme": w["scheme"], "nx": w["nx"],
                        "nt": w["nt"], "cfl": w["cfl"], "m": w["m"],
                        "levels": w["levels"], "cycle": w["cycle"], "tol": TOL,
-                       "psi_rule": w["psi_rule"], "psi_nnz": [len(o) for o, _ in psi]},
-            "iterations": r.iters, "final_residual": r.hist[-1],
-            "step_ms": {"median": round(1e3 * float(np.median(each)), 4),
-                        "p95": round(1e3 * float(np.percentile(each, 95)), 4),
-                        "min": round(1e3 * min(each), 4)},
-            "kernels": P.describe()}
-    line["roofline"] = roofline(P, w, u0, uinit, torch, a.workload)
+                       "precision": w["precision"], "psi_rule": w["psi_rule"],
+                       "psi_nnz": rec["psi_nnz"]},
+            "iterations": rec["iterations"], "final_residual": rec["final_residual"],
+            "step_ms": rec["step_ms"],
+            "error_vs_fp64_reference": rec["error_vs_fp64_reference"],
+            "reference_residual": rec.get("reference_residual"),
+            "kernels": rec["kernels"], "roofline": rec["roofline"],
+            "ms_by_class": rec["ms_by_class"], "by_pass": rec["by_pass"],
+            "fine_passes": {"fp64": rec["fine_passes_fp64"], "fp32": rec["fine_passes_fp32"]}}
     tseq = gpu_sequential(P, w, u0, torch)
     line["gpu_sequential"] = {"ms": round(tseq * 1e3, 3),
                               "dof_per_s": w["nx"] * w["nt"] / tseq,
                               "mgrit_speedup": round(tseq / dt, 2)}
     P.close()
-    if not a.no_extra:
-        extra = {}
-        if w["psi_rule"] == "bound":  # the same solve with the Sec. 4.4 width rule
-            extra[a.workload + "@window_rule"] = workload_line(a.workload, 3, 1, torch,
-                                                               psi_rule="window")
-        for name in inputs.WORKLOADS:
-            if name == a.workload:
-                continue
-            try:
-                extra[name] = workload_line(name, 3, 1, torch)
-                if inputs.WORKLOADS[name]["precision"] == "fp32":
-                    extra[name + "@fp64"] = workload_line(name, 3, 1, torch, "fp64")
-            except Exception as e:  # report, keep the main line
-                extra[name] = {"error": str(e)}
-        line["workloads"] = extra
-    if a.serve > 0 and not a.no_extra:
+    if w["precision"] == "fp32":
+        # the same solve in plain FP64, the same number of timed steps
+        P64, _, _, r64, _, dt64, _ = solve_record(a.workload, w, steps, a.warmup, torch,
+                                                  "fp64", ref)
+        P64.close()
+        line["fp64"] = r64
+        line["fp32_vs_fp64"] = {
+            "speedup_median": round(r64["step_ms"]["median"] / rec["step_ms"]["median"], 4),
+            "spread_fp32": round(rec["step_ms"]["p95"] / rec["step_ms"]["median"] - 1, 4),
+            "spread_fp64": round(r64["step_ms"]["p95"] / r64["step_ms"]["median"] - 1, 4)}
+    extra = {}
+    if w["psi_rule"] == "bound":  # the same solve with the Sec. 4.4 width rule
+        ww = dict(w, psi_rule="window")
+        Pw, _, _, rw, _, _, _ = solve_record(a.workload, ww, 5, 1, torch, None, ref)
+        Pw.close()
+        extra[a.workload + "@window_rule"] = rw
+    for name in inputs.WORKLOADS:
+        if name == a.workload:
+            continue
+        try:
+            wn = dict(inputs.WORKLOADS[name])
+            Pn, _, _, rn, refn, _, _ = solve_record(name, wn, 5, 1, torch)
+            Pn.close()
+            extra[name] = rn
+            if wn["precision"] == "fp32":
+                Pf, _, _, rf, _, _, _ = solve_record(name, wn, 5, 1, torch, "fp64", refn)
+                Pf.close()
+                extra[name + "@fp64"] = rf
+        except Exception as e:  # report, keep the main line
+            extra[name] = {"error": str(e)}
+        torch.cuda.empty_cache()
+    line["workloads"] = extra
+    if a.serve > 0:
         line["serving"] = serving(a.serve, torch)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)

@@ -339,6 +339,35 @@ int mgrit_get_stats(mgrit_plan_t plan, mgrit_stats* stats);
 int mgrit_set_profiling(mgrit_plan_t plan, int enable);
 int mgrit_get_profile(mgrit_plan_t plan, mgrit_profile* prof);
 
+/* The same timing split by level, pass and precision, with the algorithmic
+ * work of every launch: the bytes the pass must move between HBM and the
+ * chip (C-point rows read and written, right-hand side rows, rows stored
+ * by interpolation; n_x * 8 bytes per row) and its flops (2 nnz per point
+ * and step for a stencil of nnz taps, the recurrence count of the SDIRK
+ * stage solves, Sec. 2.1 and Corollary 1), so that a roofline fraction can
+ * be formed per pass.  Passes: */
+#define MGRIT_PASS_FC 0        /* F- then C-relaxation (pass A)              */
+#define MGRIT_PASS_RES 1       /* F-relaxation + C-point residual (pass B)   */
+#define MGRIT_PASS_F 2         /* F-relaxation storing every point           */
+#define MGRIT_PASS_SWEEP 3     /* coarsest level: sequential sweep           */
+#define MGRIT_PASS_SPECTRAL 4  /* coarsest level: spectral solve             */
+#define MGRIT_PASS_NORM 5      /* residual-norm reduction                    */
+#define MGRIT_PASS_COPY 6      /* C-point copies, refinement updates         */
+typedef struct {
+    int level;          /* 0 = fine                                          */
+    int pass;           /* MGRIT_PASS_*                                      */
+    int precision;      /* 0 FP64 arithmetic, 1 FP32                         */
+    long long launches;
+    double ms;          /* summed HIP-event time of the launches             */
+    double bytes;       /* summed algorithmic HBM bytes                      */
+    double flops;       /* summed algorithmic flops                          */
+} mgrit_prof_entry;
+/* Writes min(capacity, number of entries) entries, sorted by level, pass,
+ * precision; *count receives the number of entries.  Profiling must have
+ * been turned on (mgrit_set_profiling) for the launches to be counted. */
+int mgrit_get_profile_detail(mgrit_plan_t plan, mgrit_prof_entry* out,
+                             int capacity, int* count);
+
 /* Operator complexity of the plan's hierarchy, eq. (10). */
 int mgrit_operator_complexity(mgrit_plan_t plan, double* oc);
 

@@ -234,6 +234,7 @@ static bool pick_tiled(int nx, int width, int Wb, int S, int nblk, bool io, int 
 int OpDesc::init_stencil(const Taps& t, int nx, int steps, int nblk, bool seq, int max_tiles,
                          std::string& err) {
   nnz = (int)t.off.size();
+  flops_pps = 2.0 * nnz;
   std::vector<double> dense;
   int W = 1;
   tap_window(t, nx, omin, W, dense);
@@ -348,6 +349,18 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   bfn[1] = kt.sdirk_b[1][sdirk_k_index(K)][si];
   shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
   nnz = 0;
+  // algorithmic flops per point and step: each stage scales its right-hand
+  // side, runs the factors' recurrences (2 flops per coefficient), combines
+  // the earlier stage derivatives (2 per non-zero a_il) and, unless it is
+  // the last (stiffly accurate) stage, forms its derivative (2)
+  flops_pps = 0.0;
+  for (int i = 0; i < sd.s; ++i) {
+    flops_pps += 1.0;
+    for (int q = 0; q < sd.nf; ++q) flops_pps += sd.f[q].a2 != 0.0 ? 4.0 : 2.0;
+    for (int l = 0; l < i; ++l)
+      if (sd.A[i][l] != 0.0) flops_pps += 2.0;
+    if (i < sd.s - 1) flops_pps += 2.0;
+  }
   for (int p = 0; p < 2; ++p)
     if (shmem[p] > kernel_info(fn[p]).max_lds) {
       err = "n_x too large for the SDIRK kernel's LDS staging";
@@ -363,6 +376,7 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
   fn[1] = nullptr;  // FP64 state only
   bfn[1] = nullptr;
   nnz = (int)interior.off.size();
+  flops_pps = 2.0 * nnz;
   omin = stride;
   // register-blocked kernel: the taps as one dense window of a compiled
   // width, chunks of bounded_k(width) points
@@ -573,7 +587,7 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
   if (profiling) {
     e1 = take_event();
     (void)hipEventRecord(e1, stream);
-    pending.push_back({cls, e0, e1});
+    pending.push_back({cls, e0, e1, tag});
   }
   return MGRIT_OK;
 }
@@ -595,6 +609,21 @@ void Plan::collect_profile() {
     (void)hipEventElapsedTime(&ms, p.e0, p.e1);
     prof.ms[p.cls] += ms;
     prof.launches[p.cls] += 1;
+    mgrit_prof_entry* e = nullptr;
+    for (auto& d : detail)
+      if (d.level == p.tag.level && d.pass == p.tag.pass && d.precision == p.tag.prec) e = &d;
+    if (!e) {
+      mgrit_prof_entry z = {};
+      z.level = p.tag.level;
+      z.pass = p.tag.pass;
+      z.precision = p.tag.prec;
+      detail.push_back(z);
+      e = &detail.back();
+    }
+    e->launches += 1;
+    e->ms += ms;
+    e->bytes += p.tag.bytes;
+    e->flops += p.tag.flops;
     event_pool.push_back(p.e0);
     event_pool.push_back(p.e1);
   }
@@ -613,7 +642,34 @@ void Plan::end_util(int cls, hipEvent_t e0) {
   if (!profiling) return;
   hipEvent_t e1 = take_event();
   (void)hipEventRecord(e1, stream);
-  pending.push_back({cls, e0, e1});
+  pending.push_back({cls, e0, e1, tag});
+}
+
+// Algorithmic HBM bytes and flops of a relaxation launch over `grid`
+// workgroup rows: start rows (and corrections), right-hand side rows,
+// reference rows, rows written; the operator's flops per point and step.
+static ProfTag relax_tag(const OpDesc& op, const RelaxArgs& a, int grid, int level, int prec) {
+  ProfTag t;
+  t.level = level;
+  t.prec = prec;
+  t.pass = a.mode == MODE_FC ? MGRIT_PASS_FC : (a.mode == MODE_RES ? MGRIT_PASS_RES : MGRIT_PASS_F);
+  const double nint = a.nint, m = a.m;
+  double rows = 0.0;
+  if (!a.zero_in) rows += grid;
+  if (a.corr) rows += grid;
+  if (a.rhs_mode == RHS_EVERY) rows += nint * m;
+  if (a.rhs_mode == RHS_CPOINT) rows += nint;
+  if (a.mode == MODE_FC) {
+    rows += nint + (a.write_row0 ? 1 : 0);
+    if (a.delta) rows += (a.zero_in ? 0 : nint) + (a.corr ? nint : 0) + nint;
+  } else if (a.mode == MODE_RES) {
+    rows += 2.0 * nint + 1.0;  // reference rows read, residual rows (and row 0) written
+  } else {
+    rows += nint * m + (grid > a.nint ? 1 : 0) + (a.write_last ? nint : 0);
+  }
+  t.bytes = rows * a.nx * 8.0;
+  t.flops = nint * m * a.nx * (op.flops_pps + (a.rhs_mode == RHS_EVERY ? 1.0 : 0.0));
+  return t;
 }
 
 // Relaxation on level l (0 = fine).  mode: MODE_FC / MODE_RES / MODE_F.
@@ -643,6 +699,7 @@ int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride
   }
   const int grid = L.nc + (mode == MODE_F ? 1 : 0);
   if (l == 0) fine_dof_steps += (double)L.nc * steps * nx;
+  if (profiling) tag = relax_tag(op, a, grid, l, prec);
   return launch(op, prec, a, grid, l == 0 ? MGRIT_PROF_RELAX_FINE
                                           : (mode == MODE_F ? MGRIT_PROF_OTHER
                                                             : MGRIT_PROF_RELAX_COARSE));
@@ -664,6 +721,14 @@ int Plan::copy_cpoints(int l, int prec, const double* in, long long in_stride,
   a.nint = L.nc + 1;
   a.out = out;
   a.out_off = 0;
+  if (profiling) {
+    tag = ProfTag();
+    tag.level = l;
+    tag.pass = MGRIT_PASS_COPY;
+    tag.prec = prec;
+    tag.bytes = (double)(L.nc + 1) * nx * 8.0 * ((in ? 1 : 0) + (corr ? 1 : 0) + 1);
+    tag.flops = corr ? (double)(L.nc + 1) * nx : 0.0;
+  }
   return launch(op, prec, a, L.nc + 1, MGRIT_PROF_OTHER);
 }
 
@@ -688,6 +753,13 @@ int Plan::sequential_chunk(int s0, const double* g, bool* last) {
     a.nint = L.n;
     a.out = L.X;
     *last = true;
+    if (profiling) {
+      tag = ProfTag();
+      tag.level = (int)lev.size() - 1;
+      tag.pass = MGRIT_PASS_SWEEP;
+      tag.bytes = 2.0 * L.n * nx * 8.0;  // right-hand side rows in, solution rows out
+      tag.flops = (double)L.n * nx * (op.flops_pps + 1.0);
+    }
     return launch(op, 0, a, (L.n + op.nilq - 1) / op.nilq, MGRIT_PROF_COARSEST);
   }
   const int S = op.seq_chunk > 0 ? op.seq_chunk : L.n;
@@ -706,6 +778,14 @@ int Plan::sequential_chunk(int s0, const double* g, bool* last) {
   a.write_last = 1;
   a.out = L.X + (long long)s0 * nx;
   *last = s0 + S >= L.n;
+  if (profiling) {
+    tag = ProfTag();
+    tag.level = (int)lev.size() - 1;
+    tag.pass = MGRIT_PASS_SWEEP;
+    // start row (after the first launch), right-hand side rows, rows stored
+    tag.bytes = ((s0 ? 1.0 : 0.0) + 2.0 * a.m + (s0 ? 0.0 : 1.0)) * nx * 8.0;
+    tag.flops = (double)a.m * nx * (op.flops_pps + 1.0);
+  }
   return launch(op, 0, a, 1, MGRIT_PROF_COARSEST);
 }
 
@@ -1351,6 +1431,7 @@ int mgrit_set_profiling(mgrit_plan_t plan, int enable) {
   P->profiling = enable != 0;
   if (enable) {
     std::memset(&P->prof, 0, sizeof P->prof);
+    P->detail.clear();
     P->prof_dof_base = P->fine_dof_steps;
   }
   return MGRIT_OK;
@@ -1364,6 +1445,24 @@ int mgrit_get_profile(mgrit_plan_t plan, mgrit_profile* prof) {
   P->collect_profile();
   *prof = P->prof;
   prof->fine_dof_steps = P->fine_dof_steps - P->prof_dof_base;
+  return MGRIT_OK;
+}
+
+int mgrit_get_profile_detail(mgrit_plan_t plan, mgrit_prof_entry* out, int capacity,
+                             int* count) {
+  if (!plan || !count || capacity < 0 || (capacity > 0 && !out)) return MGRIT_EINVAL;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  P->collect_profile();
+  std::vector<mgrit_prof_entry> d = P->detail;
+  std::sort(d.begin(), d.end(), [](const mgrit_prof_entry& x, const mgrit_prof_entry& y) {
+    if (x.level != y.level) return x.level < y.level;
+    if (x.pass != y.pass) return x.pass < y.pass;
+    return x.precision < y.precision;
+  });
+  *count = (int)d.size();
+  for (int i = 0; i < capacity && i < (int)d.size(); ++i) out[i] = d[i];
   return MGRIT_OK;
 }
 
@@ -1412,6 +1511,7 @@ int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
     a.omin = 0;
   }
   const int prec = P->precision == MGRIT_FP32_RELAX ? 1 : 0;
+  if (P->profiling) P->tag = relax_tag(op, a, batch, 0, prec);
   return P->launch(op, prec, a, batch, MGRIT_PROF_RELAX_FINE);
 }
 

@@ -65,6 +65,7 @@ struct OpDesc {
   int NL = 0, K = 0;                    // lanes per workgroup, points per lane
   int width = 0, Wbucket = 0, omin = 0; // stencil window, compiled width, start
   int ntaps = 0, nnz = 0;
+  double flops_pps = 0.0;               // algorithmic flops per point and step
   double* d_taps = nullptr;
   int* d_off = nullptr;
   void* d_sdirk = nullptr;
@@ -129,9 +130,17 @@ struct Batch {
   int flush();
 };
 
+// What a profiled launch is: its level, pass (MGRIT_PASS_*), arithmetic
+// precision and algorithmic HBM bytes and flops.
+struct ProfTag {
+  int level = 0, pass = 0, prec = 0;
+  double bytes = 0.0, flops = 0.0;
+};
+
 struct ProfPending {
   int cls;
   hipEvent_t e0, e1;
+  ProfTag tag;
 };
 
 struct Plan {
@@ -163,6 +172,8 @@ struct Plan {
   double fine_dof_steps = 0.0, prof_dof_base = 0.0;
   std::vector<ProfPending> pending;
   std::vector<hipEvent_t> event_pool;
+  ProfTag tag;                            // of the next profiled launch
+  std::vector<mgrit_prof_entry> detail;   // per (level, pass, precision)
   int parts = 0;  // partial sums written by the last residual launch
   Batch* batch = nullptr;  // set: relaxation launches are recorded there
 

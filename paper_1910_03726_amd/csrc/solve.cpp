@@ -79,6 +79,12 @@ class Group {
     for (Member* M : l) {
       Plan* P = M->P;
       hipEvent_t e0 = nullptr;
+      if (P->profiling) {
+        P->tag = ProfTag();
+        P->tag.pass = MGRIT_PASS_NORM;
+        P->tag.bytes = P->parts * 8.0;
+        P->tag.flops = P->parts;
+      }
       P->mark_util(MGRIT_PROF_NORM, e0);
       launch_norm_reduce(P->partial, P->parts, P->scale * P->scale, P->d_norm, stream_);
       P->end_util(MGRIT_PROF_NORM, e0);
@@ -130,6 +136,16 @@ void coarse_solve(Group& G, const List& l0, int l, int kind, int prec) {
     }
     Level& L = P->lev.back();
     hipEvent_t e0 = nullptr;
+    if (P->profiling) {
+      // right-hand side rows in, solution rows out; two real transforms of
+      // 2.5 n_x log2 n_x flops per row and a complex multiply-add per mode
+      // and step
+      P->tag = ProfTag();
+      P->tag.level = (int)P->lev.size() - 1;
+      P->tag.pass = MGRIT_PASS_SPECTRAL;
+      P->tag.bytes = 2.0 * L.n * P->nx * 8.0;
+      P->tag.flops = (double)L.n * P->nx * (5.0 * std::log2((double)P->nx) + 8.0);
+    }
     P->mark_util(MGRIT_PROF_COARSEST, e0);
     Group::check(M, launch_spectral_solve(rhs_of(M, l), L.X, P->Sspec, L.seq.d_mu,
                                           L.seq.d_tw, P->nx, L.n, G.stream()) == 0
@@ -425,6 +441,12 @@ void solve_ir(Group& G, const List& all) {
       Plan* P = M->P;
       const long long cells = (long long)(P->nt / P->m + 1) * P->nx;
       hipEvent_t e0 = nullptr;
+      if (P->profiling) {
+        P->tag = ProfTag();
+        P->tag.pass = MGRIT_PASS_COPY;
+        P->tag.bytes = 3.0 * cells * 8.0;
+        P->tag.flops = (double)cells;
+      }
       P->mark_util(MGRIT_PROF_OTHER, e0);
       launch_axpy(P->U, M->nxt, cells, G.stream());
       P->end_util(MGRIT_PROF_OTHER, e0);

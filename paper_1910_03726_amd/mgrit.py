@@ -55,6 +55,15 @@ class Profile(ctypes.Structure):
                 ("fine_dof_steps", ctypes.c_double)]
 
 
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("pass_", ctypes.c_int), ("precision", ctypes.c_int),
+                ("launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double), ("flops", ctypes.c_double)]
+
+
+PASSES = ("fc", "res", "f", "sweep", "spectral", "norm", "copy")
+
+
 class Request(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("nt", ctypes.c_int), ("scheme", ctypes.c_int),
                 ("m", ctypes.c_int), ("levels", ctypes.c_int), ("cycle", ctypes.c_int),
@@ -152,6 +161,8 @@ _SIGS = {
     "mgrit_set_profiling": (_I, [_P, _I]),
     "mgrit_get_profile": (_I, [_P, ctypes.POINTER(Profile)]),
     "mgrit_operator_complexity": (_I, [_P, ctypes.POINTER(_D)]),
+    "mgrit_get_profile_detail": (_I, [_P, ctypes.POINTER(ProfEntry), _I,
+                                      ctypes.POINTER(_I)]),
     "mgrit_plan_describe": (ctypes.c_char_p, [_P]),
     "mgrit_destroy": (None, [_P]),
     "mgrit_solve_static": (_I, [_I, _I, _D, _D, _I, _I, _I, ctypes.POINTER(Taps), _I, _I,
@@ -453,6 +464,20 @@ class Plan:
         return {"ms": dict(zip(PROF_CLASSES, list(p.ms))),
                 "launches": dict(zip(PROF_CLASSES, list(p.launches))),
                 "fine_dof_steps": p.fine_dof_steps}
+
+    def profile_detail(self):
+        """Per (level, pass, precision): launches, ms and the algorithmic
+        HBM bytes and flops of the profiled launches
+        (mgrit_get_profile_detail)."""
+        n = _I()
+        _check(lib().mgrit_get_profile_detail(self._h, None, 0, ctypes.byref(n)),
+               "mgrit_get_profile_detail")
+        arr = (ProfEntry * max(1, n.value))()
+        _check(lib().mgrit_get_profile_detail(self._h, arr, n.value, ctypes.byref(n)),
+               "mgrit_get_profile_detail")
+        return [{"level": e.level, "pass": PASSES[e.pass_],
+                 "precision": ("fp64", "fp32")[e.precision], "launches": e.launches,
+                 "ms": e.ms, "bytes": e.bytes, "flops": e.flops} for e in arr[:n.value]]
 
     def operator_complexity(self):
         v = _D()

@@ -21,7 +21,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 @pytest.mark.parametrize("workload,source", [
+    ("erk5_u5_nx8192_nt65536_m8_fp32relax", "relax_kernels.h"),
     ("erk3_u3_nx4096_nt16384_m8_fcycle", "relax_kernels.h"),
+    ("sdirk3_u3_nx2048_nt8192_m16_2level", "sdirk_kernels.h"),
     ("erk3_u3_inflow_nx4096_nt16384_m8_vcycle", "bounded_kernels.h"),
 ])
 def test_committed_counters_match_the_kernel_sources(workload, source):
@@ -33,6 +35,6 @@ def test_committed_counters_match_the_kernel_sources(workload, source):
     text = open(os.path.join(ROOT, "profiles", f"{workload}_hbm_counters.txt")).read()
     assert f"kernel source ({source}) sha256[:16]: {sha}" in text
     t = bench.measured_traffic(workload, source)
-    assert t is not None and 1e8 < t < 1e9
+    assert t is not None and 1e7 < t < 1e10
     # and a mismatching source gives no traffic
     assert bench.measured_traffic(workload, "spectral.hip") is None
