@@ -6,8 +6,12 @@
  * of De Sterck et al., arXiv:1910.03726) with the least-squares coarse
  * operators of Sec. 4 (rule MGRIT_PSI_AUTO).  Life of a request:
  *   submit   -> the server copies u0 and queues the host setup of Psi on a
- *               worker thread (Psi is cached per scheme, Courant number,
- *               n_x, m and number of levels);
+ *               worker thread.  Psi is cached per (scheme, Courant
+ *               number, m): a request whose n_x divides the n_x of a cached
+ *               hierarchy with enough levels takes its stencils folded onto
+ *               n_x points, otherwise it gets its own fit, which is cached.
+ *               Psi decides only how fast a solve converges, not what it
+ *               converges to (the fine system's solution, Sec. 2.2);
  *   admit    -> when a slot is free and the plan's device footprint
  *               (mgrit_plan_estimate_bytes) fits the HBM budget next to the
  *               plans already resident; requests whose setup is done are

@@ -9,7 +9,9 @@
 // memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -47,7 +49,23 @@ struct Req {
   std::vector<double> ufinal;
 };
 
-using PsiKey = std::tuple<int, unsigned long long, int, int, int>;
+// The coarse-operator cache, keyed by (scheme, Courant number, m).  An
+// entry holds the eq. (9) hierarchy computed for some n_x_ref, deep enough
+// for every request it served (a hierarchy of L levels is the first L-1
+// operators of a deeper one).  A request on n_x points with n_x dividing
+// n_x_ref takes the stencils folded onto its periodic line (offsets mod n_x):
+// the circulant that the n_x_ref one folds to, fitted on a superset of its
+// modes (theta_k on n_x points is theta_{k n_x_ref/n_x} on the longer line).
+// Psi decides only how fast MGRIT converges, not its fixed point (Sec. 2.2).
+// The Courant number is matched exactly: Psi_l approximates Phi^(m^(l-1)),
+// whose characteristic shift of c m^(l-1) points moves by whole grid points
+// on deep levels for Courant numbers 1 % apart, which stalls or breaks the
+// convergence.
+using PsiKey = std::tuple<int, unsigned long long, int>;
+struct PsiEntry {
+  int nx = 0;
+  std::vector<Taps> ops;  // offsets in [0, nx)
+};
 
 struct Server {
   std::mutex mu;
@@ -57,7 +75,7 @@ struct Server {
   std::deque<std::shared_ptr<Req>> setup_q;
   std::list<std::shared_ptr<Req>> ready_q;  // by submission order
   std::deque<Group> run_q;
-  std::map<PsiKey, std::vector<Taps>> psi_cache;
+  std::map<PsiKey, std::vector<PsiEntry>> psi_cache;
   long long next_id = 1, submitted = 0, completed = 0, admitted = 0, hits = 0, misses = 0;
   size_t budget = 0, in_use = 0, peak = 0;
   int free_slots = 0, max_bypass = 0, max_batch = 1, device = 0;
@@ -65,11 +83,19 @@ struct Server {
   bool stopping = false;
   std::vector<std::thread> workers;
 
-  // Requests whose relaxation launches can merge: the same plan shapes.
+  // Requests run as one group: the same line (n_x), scheme, coarsening
+  // factor, cycle, relaxation and precision, so that the fine-level passes --
+  // most of a solve -- have the same stencil kernel, and n_t within a factor
+  // of two (the number of levels may differ by one): a group returns when
+  // its last member has converged, so members of very different size would
+  // hold the small ones back.  Launches of the same kernel and launch shape
+  // merge into one grid (Batch in plan.h); the others of the group go out
+  // one after another on its stream.
   static bool same_shape(const Req& a, const Req& b) {
-    return a.r.nx == b.r.nx && a.r.nt == b.r.nt && a.r.scheme == b.r.scheme &&
-           a.r.m == b.r.m && a.levels == b.levels && a.r.cycle == b.r.cycle &&
-           a.r.relax == b.r.relax && a.r.precision == b.r.precision;
+    const int lo = std::min(a.r.nt, b.r.nt), hi = std::max(a.r.nt, b.r.nt);
+    return a.r.nx == b.r.nx && a.r.scheme == b.r.scheme && a.r.m == b.r.m &&
+           a.r.cycle == b.r.cycle && a.r.relax == b.r.relax &&
+           a.r.precision == b.r.precision && hi <= 2 * (long long)lo;
   }
 
   void admit(Req& q, Group& g, const std::shared_ptr<Req>& sp) {
@@ -134,6 +160,56 @@ struct Server {
     }
   }
 
+  // Psi_2..Psi_L for request q (L = q.levels) on its n_x: folded from a
+  // cached hierarchy on a multiple of n_x points, or fitted for the request
+  // (and cached) on a miss.
+  int coarse_operators(const Req& q, std::vector<Taps>& psi) {
+    const mgrit_request& r = q.r;
+    PsiKey key{r.scheme, 0ULL, r.m};
+    std::memcpy(&std::get<1>(key), &r.cfl, sizeof(double));
+    PsiEntry hit;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto f = psi_cache.find(key);
+      if (f != psi_cache.end())
+        for (const PsiEntry& e : f->second)
+          if (e.nx % r.nx == 0 && (int)e.ops.size() >= q.levels - 1 && e.nx > hit.nx) hit = e;
+      ++(hit.nx ? hits : misses);
+    }
+    if (!hit.nx) {
+      double mi = 0.0;
+      int rc;
+      try {
+        rc = psi_hierarchy(r.scheme, r.cfl, r.nx, r.m, q.levels, MGRIT_PSI_AUTO, nullptr, 0.0,
+                           psi, mi);
+      } catch (...) {
+        rc = MGRIT_ENOMEM;
+      }
+      if (rc != MGRIT_OK) return rc;
+      std::lock_guard<std::mutex> lk(mu);
+      auto& es = psi_cache[key];
+      bool have = false;
+      for (PsiEntry& e : es)
+        if (e.nx == r.nx) {
+          if (e.ops.size() < psi.size()) e.ops = psi;
+          have = true;
+        }
+      if (!have) es.push_back({r.nx, psi});
+      return MGRIT_OK;
+    }
+    psi.assign(q.levels - 1, Taps());
+    for (int l = 0; l < q.levels - 1; ++l) {
+      std::map<int, double> folded;
+      for (size_t t = 0; t < hit.ops[l].off.size(); ++t)
+        folded[hit.ops[l].off[t] % r.nx] += hit.ops[l].w[t];
+      for (auto& a : folded) {
+        psi[l].off.push_back(a.first);
+        psi[l].w.push_back(a.second);
+      }
+    }
+    return MGRIT_OK;
+  }
+
   void setup_loop() {
     for (;;) {
       std::shared_ptr<Req> q;
@@ -144,33 +220,8 @@ struct Server {
         q = setup_q.front();
         setup_q.pop_front();
       }
-      const mgrit_request& r = q->r;
-      PsiKey key{r.scheme, 0ULL, r.nx, r.m, q->levels};
-      std::memcpy(&std::get<1>(key), &r.cfl, sizeof(double));
       std::vector<Taps> psi;
-      bool hit = false;
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        auto f = psi_cache.find(key);
-        if (f != psi_cache.end()) {
-          psi = f->second;
-          hit = true;
-          ++hits;
-        }
-      }
-      int rc = MGRIT_OK;
-      if (!hit) {
-        double mi = 0.0;
-        try {
-          rc = psi_hierarchy(r.scheme, r.cfl, r.nx, r.m, q->levels, MGRIT_PSI_AUTO, nullptr,
-                             0.0, psi, mi);
-        } catch (...) {
-          rc = MGRIT_ENOMEM;
-        }
-        std::lock_guard<std::mutex> lk(mu);
-        ++misses;
-        if (rc == MGRIT_OK) psi_cache[key] = psi;
-      }
+      int rc = coarse_operators(*q, psi);
       std::lock_guard<std::mutex> lk(mu);
       if (rc != MGRIT_OK) {
         q->res.status = rc;

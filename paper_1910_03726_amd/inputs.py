@@ -142,14 +142,15 @@ def serving_requests(n, seed=7, nx_exps=range(8, 14), nt_exps=range(10, 16),
                      orders=(1, 3, 5), ms=(4, 8)):
     """The serving mix: n requests with n_x = 2^a (a in nx_exps), n_t = 2^b
     (b in nt_exps), ERKp+Up with p in orders, CFL fraction U[0.5, 0.9] of the
-    Table 1 limit, m in ms, FP32 relaxation or FP64 with probability 1/2 each,
-    u0 = 8 seeded Fourier modes, and a seed for the initial iterate.
-    Arrival times are drawn separately (``poisson_arrivals``)."""
+    Table 1 limit rounded to 0.01 (clients pick the Courant number from a
+    menu of 41 values), m in ms, FP32 relaxation or FP64 with probability
+    1/2 each, u0 = 8 seeded Fourier modes, and a seed for the initial
+    iterate.  Arrival times are drawn separately (``poisson_arrivals``)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
         p = int(rng.choice(orders))
-        frac = float(rng.uniform(0.5, 0.9))
+        frac = round(float(rng.uniform(0.5, 0.9)), 2)
         out.append(dict(
             nx=int(2 ** rng.choice(list(nx_exps))),
             nt=int(2 ** rng.choice(list(nt_exps))),

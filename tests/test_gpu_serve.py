@@ -5,7 +5,10 @@
   kernels are deterministic and requests share no state;
 * admission never exceeds the HBM budget; a request that does not fit is
   passed at most max_bypass times (no starvation);
-* results agree with the oracle's sequential stepping.
+* results agree with the oracle (sequential stepping; the closed form of
+  Lemma 1 for a full-size sample of the bench mix);
+* the coarse-operator cache serves requests of the same scheme, Courant
+  number and m on shorter lines.
 """
 
 import time
@@ -154,3 +157,55 @@ def test_estimate_bounds_plan_bytes():
             b = P.bytes()
         est = M.estimate_bytes(nx, nt, m, L, prec)
         assert b <= est <= b + L * 64 * 1024
+
+
+def test_full_size_mix_sample_matches_the_oracle():
+    # the largest requests of the bench's 2000-request mix (n_x = 8192,
+    # n_t = 32768, ERK1/3/5, FP32 relaxation and FP64), solved to the mix's
+    # tolerance 1e-10 in one server, against the extended-precision closed
+    # form of Lemma 1; the error is the iteration's (|A^-1| |r|)
+    reqs = inputs.serving_requests(2000, seed=7)
+    big = sorted(reqs, key=lambda q: -q["nx"] * q["nt"])
+    sample = []
+    for p in (1, 3, 5):
+        for prec in ("fp64", "fp32"):
+            sample += [q for q in big if q["p"] == p and q["precision"] == prec][:1]
+    with M.Server(200 * GiB, slots=4, setup_threads=4) as S:
+        ids = [_submit(S, q) for q in sample]
+        for q, i in zip(sample, ids):
+            res, u = S.wait(i, q["nx"])
+            print(q["scheme"], q["precision"], q["nx"], q["nt"], q["m"], res.iterations,
+                  res.final_residual, flush=True)
+            assert res.status == M.OK, res.status
+            d = rk.Discretization(q["scheme"], q["nx"], q["cfl"])
+            ref = d.spectral_propagate(inputs.request_u0(q), q["nt"])
+            assert np.max(np.abs(u - ref)) / np.max(np.abs(ref)) < 1e-8
+
+
+def test_cached_psi_hits_and_converges_like_the_own_fit():
+    # one (scheme, Courant number, m) entry fitted on 2048 points serves the
+    # requests on 1024, 512 and 256 points (its stencils folded onto their
+    # lines); each converges to its own solution in at most one iteration
+    # more than with its own eq. (9) fit
+    base = _mix(1, seed=21)[0]
+    reqs = []
+    for k, (nx, nt) in enumerate(((2048, 4096), (1024, 2048), (512, 2048), (256, 1024))):
+        q = dict(base, nx=nx, nt=nt, m=4, scheme="ERK3", precision="fp64",
+                 init_seed=70 + k, u0_seed=700 + k, cfl=rk.paper_cfl("ERK3", 0.7))
+        reqs.append(q)
+    with M.Server(64 * GiB, slots=1, setup_threads=1) as S:
+        got = [S.wait(_submit(S, q), q["nx"]) for q in reqs]
+        st = S.stats()
+    assert st.psi_cache_hits == len(reqs) - 1 and st.psi_cache_misses == 1
+    import torch
+    for q, (res, u) in zip(reqs, got):
+        assert res.status == M.OK
+        psi, _ = M.psi_optimize(q["scheme"], q["cfl"], q["nx"], q["m"], res.levels)
+        with M.Plan(q["nx"], q["nt"], q["cfl"], q["scheme"], q["m"], res.levels, psi) as P:
+            P.set_seed(q["init_seed"])
+            r = P.solve(torch.tensor(inputs.request_u0(q), device="cuda:0"), None,
+                        tol=1e-10, maxit=100, out="final")
+        print(q["nx"], q["nt"], res.levels, "cached", res.iterations, "own", r.iters)
+        assert res.iterations <= r.iters + 1, (q, res.iterations, r.iters)
+        ref = r.out.cpu().numpy()[0]
+        assert np.max(np.abs(u - ref)) / np.max(np.abs(ref)) < 1e-8
