@@ -142,7 +142,7 @@ def _kernel_source(w):
     if w.get("boundary") == "inflow":
         return "bounded_kernels.h", "k_bounded_tiled"
     if w["scheme"].startswith("SDIRK"):
-        return "sdirk_kernels.h", "k_sdirk"
+        return "sdirk_pf_kernels.h", "k_sdirk_pf"
     return "relax_kernels.h", "k_stencil"
 
 

@@ -42,6 +42,8 @@ def _jobs():
     for prec in (0, 1):
         objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk.hip"),
                      f"inst_sdirk_{prec}.o", [f"-DMGR_PREC={prec}"]))
+        objs.append((HIPCC, os.path.join(CSRC, "inst_sdirk_pf.hip"),
+                     f"inst_sdirk_pf_{prec}.o", [f"-DMGR_PREC={prec}"]))
         for k in STENCIL_K:
             objs.append((HIPCC, os.path.join(CSRC, "inst_stencil.hip"),
                          f"inst_stencil_{prec}_{k}.o",

@@ -131,4 +131,32 @@ struct SdirkDev {
   RecDev f[MAX_FACTORS];
 };
 
+// The same stage solve in partial fractions: with the stage matrix's roots
+// simple, M^{-1} = c0 I + sum_t A_t (I - q_t X_t)^{-1}, X_t = S (forward,
+// dir = +1: y_i = x_i + q y_{i-1}) or S^{-1} (backward, dir = -1:
+// y_i = x_i + q y_{i+1}), every term a first-order periodic recurrence on
+// the same right-hand side, so that all terms of a stage share one local
+// pass, one carry scan and one barrier.  Real roots give real terms; a
+// conjugate pair gives one complex term contributing 2 Re(A y).  Scan
+// constants as for RecDev, of the scalar (complex) chunk factor Q = q^K:
+// Qp[d] = Q^(2^d) and close = (1 - Q^NL)^{-1}; complex values as (re, im).
+constexpr int MAX_PF_TERMS = 4;
+struct PfTermDev {
+  int dir;
+  int pad_;
+  double q[2], a[2];
+  double Qp[11][2];
+  double close[2];
+};
+struct SdirkPfDev {
+  int s;                  // stages
+  int nr, nb, nc;         // real terms (the last nb of them backward), then
+                          // complex terms (forward)
+  int K, NL;
+  double A[MAX_STAGES][MAX_STAGES];
+  double inv_gamma;
+  double c0;
+  PfTermDev t[MAX_PF_TERMS];
+};
+
 }  // namespace mgr

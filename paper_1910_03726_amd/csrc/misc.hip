@@ -13,6 +13,8 @@ MGR_DECL_K(1) MGR_DECL_K(2) MGR_DECL_K(4) MGR_DECL_K(8) MGR_DECL_K(16) MGR_DECL_
 #undef MGR_DECL_K
 void register_sdirk_0(KernelTable&);
 void register_sdirk_1(KernelTable&);
+void register_sdirk_pf_0(KernelTable&);
+void register_sdirk_pf_1(KernelTable&);
 void register_bounded(KernelTable&);
 
 int width_index(int W) {
@@ -36,6 +38,14 @@ int sdirk_shape_index(int S, int NF) {
   return -1;
 }
 
+int sdirk_pf_shape_index(int S, int NR, int NB, int NC) {
+  for (int i = 0; i < kNumSdirkPfShapes; ++i)
+    if (kSdirkPfShapes[i][0] == S && kSdirkPfShapes[i][1] == NR &&
+        kSdirkPfShapes[i][2] == NB && kSdirkPfShapes[i][3] == NC)
+      return i;
+  return -1;
+}
+
 static KernelTable build_table() {
   KernelTable t;
 #define MGR_REG_K(K) register_stencil_0_##K(t); register_stencil_1_##K(t);
@@ -43,6 +53,8 @@ static KernelTable build_table() {
 #undef MGR_REG_K
   register_sdirk_0(t);
   register_sdirk_1(t);
+  register_sdirk_pf_0(t);
+  register_sdirk_pf_1(t);
   register_bounded(t);
   return t;
 }

@@ -337,22 +337,11 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   NL = nx / K;
   SdirkDev sd;
   if (!sdirk_setup(t, cfl, K, NL, sd, err)) return MGRIT_EINVAL;
-  const int si = sdirk_shape_index(sd.s, sd.nf);
-  if (si < 0) {
-    err = "no SDIRK kernel for this stage/factor count";
-    return MGRIT_EINVAL;
-  }
-  kind = OP_SDIRK;
-  fn[0] = kt.sdirk[0][sdirk_k_index(K)][si];
-  fn[1] = kt.sdirk[1][sdirk_k_index(K)][si];
-  bfn[0] = kt.sdirk_b[0][sdirk_k_index(K)][si];
-  bfn[1] = kt.sdirk_b[1][sdirk_k_index(K)][si];
-  shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
-  nnz = 0;
-  // algorithmic flops per point and step: each stage scales its right-hand
-  // side, runs the factors' recurrences (2 flops per coefficient), combines
-  // the earlier stage derivatives (2 per non-zero a_il) and, unless it is
-  // the last (stiffly accurate) stage, forms its derivative (2)
+  // algorithmic flops per point and step, from the factored form: each
+  // stage scales its right-hand side, runs the factors' recurrences (2 flops
+  // per coefficient), combines the earlier stage derivatives (2 per non-zero
+  // a_il) and, unless it is the last (stiffly accurate) stage, forms its
+  // derivative (2)
   flops_pps = 0.0;
   for (int i = 0; i < sd.s; ++i) {
     flops_pps += 1.0;
@@ -361,6 +350,37 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
       if (sd.A[i][l] != 0.0) flops_pps += 2.0;
     if (i < sd.s - 1) flops_pps += 2.0;
   }
+  kind = OP_SDIRK;
+  nnz = 0;
+  shmem[0] = shmem[1] = sizeof(double) * (size_t)(nx + nx / K);  // staging
+  // the partial-fraction kernel when the roots allow it and it compiles
+  // without spills, else the factored one
+  SdirkPfDev pf;
+  std::string pf_err;
+  if (sdirk_setup_pf(t, cfl, K, NL, pf, pf_err)) {
+    const int pi = sdirk_pf_shape_index(pf.s, pf.nr, pf.nb, pf.nc);
+    const int ki = sdirk_k_index(K);
+    if (pi >= 0 && ki >= 0 && kt.sdirk_pf[0][ki][pi] && kt.sdirk_pf[1][ki][pi] &&
+        !spills(kt.sdirk_pf[0][ki][pi]) && !spills(kt.sdirk_pf[1][ki][pi]) &&
+        shmem[0] <= kernel_info(kt.sdirk_pf[0][ki][pi]).max_lds &&
+        shmem[1] <= kernel_info(kt.sdirk_pf[1][ki][pi]).max_lds) {
+      fn[0] = kt.sdirk_pf[0][ki][pi];
+      fn[1] = kt.sdirk_pf[1][ki][pi];
+      bfn[0] = kt.sdirk_pf_b[0][ki][pi];
+      bfn[1] = kt.sdirk_pf_b[1][ki][pi];
+      sdirk_terms = pf.nr + pf.nc;
+      return upload(&d_sdirk, &pf, sizeof(SdirkPfDev));
+    }
+  }
+  const int si = sdirk_shape_index(sd.s, sd.nf);
+  if (si < 0) {
+    err = "no SDIRK kernel for this stage/factor count";
+    return MGRIT_EINVAL;
+  }
+  fn[0] = kt.sdirk[0][sdirk_k_index(K)][si];
+  fn[1] = kt.sdirk[1][sdirk_k_index(K)][si];
+  bfn[0] = kt.sdirk_b[0][sdirk_k_index(K)][si];
+  bfn[1] = kt.sdirk_b[1][sdirk_k_index(K)][si];
   for (int p = 0; p < 2; ++p)
     if (shmem[p] > kernel_info(fn[p]).max_lds) {
       err = "n_x too large for the SDIRK kernel's LDS staging";
@@ -517,6 +537,8 @@ std::string OpDesc::describe() const {
     snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s%s", kw, ntaps, NL,
              d_extra.empty() ? "" : " +boundary rows", nq);
   }
+  else if (sdirk_terms)
+    snprintf(buf, sizeof buf, "sdirk_pf<K=%d,terms=%d> NL=%d", K, sdirk_terms, NL);
   else
     snprintf(buf, sizeof buf, "sdirk<K=%d> NL=%d", K, NL);
   return buf;

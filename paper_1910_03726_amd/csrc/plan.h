@@ -68,7 +68,8 @@ struct OpDesc {
   double flops_pps = 0.0;               // algorithmic flops per point and step
   double* d_taps = nullptr;
   int* d_off = nullptr;
-  void* d_sdirk = nullptr;
+  void* d_sdirk = nullptr;              // SDIRK: device SdirkPfDev (sdirk_terms > 0)
+  int sdirk_terms = 0;                  // or SdirkDev (the factored form)
   void* d_bnd = nullptr;                // bounded kernel: device BoundedDev
   int nilq = 0;                         // bounded coarse operator with every offset
                                         // >= 1: Psi^nilq = 0 (else 0)

@@ -23,13 +23,23 @@ constexpr int kSdirkKs[kNumSdirkK] = {1, 2, 4, 8, 16};
 constexpr int kNumSdirkShapes = 4;
 constexpr int kSdirkShapes[kNumSdirkShapes][2] = {{1, 1}, {2, 1}, {3, 2}, {5, 3}};
 
+// SDIRK in partial fractions: (stages S, real terms NR, of which backward
+// NB, complex terms NC); with U1-U4 at most one root of the stage matrix
+// lies inside the unit circle, so the backward term is real
+constexpr int kNumSdirkPfShapes = 7;
+constexpr int kSdirkPfShapes[kNumSdirkPfShapes][4] = {
+    {1, 1, 0, 0}, {2, 2, 0, 0}, {2, 0, 0, 1}, {3, 3, 1, 0}, {3, 1, 1, 1}, {5, 4, 1, 0},
+    {5, 2, 1, 1}};
+
 struct KernelTable {
   KernelFn stencil[2][kNumK][kNumWidths][2] = {};  // [prec][K][W][per-step IO]
   KernelFn sdirk[2][kNumSdirkK][kNumSdirkShapes] = {};
+  KernelFn sdirk_pf[2][kNumSdirkK][kNumSdirkPfShapes] = {};
   KernelFn generic[2] = {};
   // batched entries of the same kernels, same indices
   BatchFn stencil_b[2][kNumK][kNumWidths][2] = {};
   BatchFn sdirk_b[2][kNumSdirkK][kNumSdirkShapes] = {};
+  BatchFn sdirk_pf_b[2][kNumSdirkK][kNumSdirkPfShapes] = {};
   BatchFn generic_b[2] = {};
   // inflow/outflow boundaries (bounded_kernels.h), FP64 state: point by
   // point, and register-blocked (K = bounded_k(W) points per thread) for the
@@ -55,6 +65,7 @@ int width_index(int W);         // index into kWidths, -1 if absent
 int k_index(int K);             // index into kKs, -1 if absent
 int sdirk_k_index(int K);
 int sdirk_shape_index(int S, int NF);
+int sdirk_pf_shape_index(int S, int NR, int NB, int NC);  // -1 if absent
 
 // Utility kernels (misc.hip).
 void launch_norm_reduce(const double* partial, int n, double scale2, double* out,

@@ -1185,4 +1185,240 @@ bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// SDIRK stage matrix in partial fractions (SdirkPfDev)
+// ---------------------------------------------------------------------------
+// With z the symbol of the shift S (z = e^{-i theta} on Fourier mode theta),
+// M(z) = sum_j coef_j z^{-j} and z^{jmax} M(z) = P(z).  Every simple root rho
+// of P gives one term of 1/M: outside the unit circle a forward recurrence
+// (1 - q z)^{-1}, q = 1/rho, with residue A = -q / M'(rho); inside a
+// backward one (1 - rho z^{-1})^{-1}, q = rho, with A = (1/rho) / M'(rho);
+// c0 = 1/M(infinity) - sum of the backward residues.  Computed in extended
+// precision; the FP64 constants are the nearest ones, with c0 and the term
+// coefficient of finest spacing moved by up to kReach units in the last
+// place where that reproduces M^{-1} on the constant mode and long waves
+// (theta <= 0.04) more closely (each rounding error there is repeated in
+// every stage of every step).
+bool sdirk_setup_pf(const Tableau& t, double cfl, int K, int NL, SdirkPfDev& out,
+                    std::string& err) {
+  out = SdirkPfDev();
+  if (!t.implicit) {
+    err = "not an SDIRK scheme";
+    return false;
+  }
+  for (int i = 1; i < t.s; ++i)
+    if (std::fabs(t.A[i][i] - t.A[0][0]) > 1e-15) {
+      err = "tableau is not singly diagonal";
+      return false;
+    }
+  TableauOf<ld> tl;
+  if (!tableau_of(t.p + 10, tl)) {
+    err = "unknown SDIRK scheme";
+    return false;
+  }
+  const ld gl = tl.A[0][0];
+  std::map<int, ld> coef;
+  for (const UpwindTerm& u : upwind_terms(t.p))
+    coef[u.off] += gl * (ld)cfl * ((ld)u.num / (ld)u.den);
+  coef[0] += 1.0L;
+  const int jmin = coef.begin()->first, jmax = coef.rbegin()->first;
+  const int D = jmax - jmin;
+  std::vector<ld> p(D + 1, 0.0L);
+  for (auto& c : coef) p[jmax - c.first] = c.second;
+  std::vector<cld> roots = poly_roots(p);
+  auto Mof = [&](cld z) {
+    cld v = 0.0L;
+    for (auto& c : coef) v += c.second * std::pow(z, -c.first);
+    return v;
+  };
+  auto dMof = [&](cld z) {
+    cld v = 0.0L;
+    for (auto& c : coef) v += -(ld)c.first * c.second * std::pow(z, -c.first - 1);
+    return v;
+  };
+  struct Term {
+    int dir;
+    cld q, a;
+    bool cx;
+  };
+  std::vector<Term> real, cplx;
+  for (const cld& rho : roots) {
+    const ld mag = std::abs(rho);
+    if (std::fabs(mag - 1.0L) < 1e-10L) {
+      err = "stage matrix has a root on the unit circle";
+      return false;
+    }
+    const bool is_real = std::fabs(rho.imag()) <= 1e-12L * mag;
+    if (!is_real && rho.imag() < 0) continue;  // its conjugate carries the pair
+    const cld r = is_real ? cld(rho.real(), 0.0L) : rho;
+    const cld dm = dMof(r);
+    Term tm;
+    if (mag > 1.0L) {
+      tm.dir = +1;
+      tm.q = 1.0L / r;
+      tm.a = -tm.q / dm;
+    } else {
+      tm.dir = -1;
+      tm.q = r;
+      tm.a = (1.0L / r) / dm;
+    }
+    tm.cx = !is_real;
+    if (tm.cx) cplx.push_back(tm);
+    else {
+      tm.q = cld(tm.q.real(), 0.0L);
+      tm.a = cld(tm.a.real(), 0.0L);
+      real.push_back(tm);
+    }
+  }
+  if ((int)(real.size() + 2 * cplx.size()) != D) {
+    err = "stage matrix roots are not simple";
+    return false;
+  }
+  if (real.size() + cplx.size() > (size_t)MAX_PF_TERMS) {
+    err = "too many partial-fraction terms";
+    return false;
+  }
+  const ld m_inf = jmin < 0 ? 0.0L : 1.0L / coef[0];  // 1/M at z -> infinity
+  ld c0 = m_inf;
+  for (const Term& tm : real)
+    if (tm.dir < 0) c0 -= tm.a.real();
+  for (const Term& tm : cplx)
+    if (tm.dir < 0) c0 -= 2.0L * tm.a.real();
+  // order: forward real terms, backward real terms, complex terms (which
+  // the kernels run forward)
+  std::stable_sort(real.begin(), real.end(),
+                   [](const Term& x, const Term& y) { return x.dir > y.dir; });
+  for (const Term& tm : cplx)
+    if (tm.dir < 0) {
+      err = "complex root inside the unit circle";
+      return false;
+    }
+  int nb = 0;
+  for (const Term& tm : real) nb += tm.dir < 0;
+  std::vector<Term> terms = real;
+  terms.insert(terms.end(), cplx.begin(), cplx.end());
+  // the decomposition and its conditioning on the unit circle
+  auto sum_terms = [&](const std::vector<Term>& ts, ld c, cld z, ld* absum) {
+    cld v = c;
+    ld sa = std::fabs(c);
+    for (const Term& tm : ts) {
+      const cld X = tm.dir > 0 ? z : 1.0L / z;
+      const cld w = tm.a / (1.0L - tm.q * X);
+      if (tm.cx) {
+        const cld wc = std::conj(tm.a) / (1.0L - std::conj(tm.q) * X);
+        v += w + wc;
+        sa += std::abs(w) + std::abs(wc);
+      } else {
+        v += w;
+        sa += std::abs(w);
+      }
+    }
+    if (absum) *absum = sa;
+    return v;
+  };
+  const ld kPi2 = 6.283185307179586476925286766559L;
+  for (int k = 0; k < 64; ++k) {
+    const cld z = std::exp(cld(0.0L, -kPi2 * k / 64));
+    const cld f = 1.0L / Mof(z);
+    ld sa = 0.0L;
+    const cld v = sum_terms(terms, c0, z, &sa);
+    if (std::abs(v - f) > 1e-14L * std::abs(f)) {
+      err = "partial-fraction check failed";
+      return false;
+    }
+    if (sa > 64.0L * std::abs(f)) {
+      err = "partial-fraction terms cancel (nearly repeated roots)";
+      return false;
+    }
+  }
+  // FP64 constants, searched around the nearest values
+  const int nt = (int)terms.size();
+  std::vector<double> qd(2 * nt), ad(2 * nt);
+  for (int i = 0; i < nt; ++i) {
+    qd[2 * i] = (double)terms[i].q.real();
+    qd[2 * i + 1] = (double)terms[i].q.imag();
+    ad[2 * i] = (double)terms[i].a.real();
+    ad[2 * i + 1] = (double)terms[i].a.imag();
+  }
+  const ld kTheta[4] = {0.0L, 0.01L, 0.02L, 0.04L};
+  auto mismatch = [&](double c0d, const std::vector<double>& a) {
+    std::vector<Term> ts = terms;
+    for (int i = 0; i < nt; ++i) {
+      ts[i].q = cld((ld)qd[2 * i], (ld)qd[2 * i + 1]);
+      ts[i].a = cld((ld)a[2 * i], (ld)a[2 * i + 1]);
+    }
+    ld worst = 0.0L;
+    for (ld th : kTheta) {
+      const cld z = std::exp(cld(0.0L, -th));
+      worst = std::max(worst, std::abs(sum_terms(ts, (ld)c0d, z, nullptr) * Mof(z) - 1.0L));
+    }
+    return worst;
+  };
+  constexpr int kReach = 12;
+  auto shifted = [](double v, int k) {
+    for (; k > 0; --k) v = std::nextafter(v, HUGE_VAL);
+    for (; k < 0; ++k) v = std::nextafter(v, -HUGE_VAL);
+    return v;
+  };
+  int fine = -1;  // the non-zero coefficient component of finest spacing
+  for (int i = 0; i < 2 * nt; ++i)
+    if (ad[i] != 0.0 && (fine < 0 || std::fabs(ad[i]) < std::fabs(ad[fine]))) fine = i;
+  double c0d = (double)c0;
+  {
+    double best_c = c0d;
+    std::vector<double> best_a = ad;
+    ld bm = mismatch(c0d, ad);
+    const double c0n = c0d;
+    for (int k0 = -kReach; k0 <= kReach; ++k0)
+      for (int k1 = (fine < 0 ? 0 : -kReach); k1 <= (fine < 0 ? 0 : kReach); ++k1) {
+        std::vector<double> a = ad;
+        if (fine >= 0) a[fine] = shifted(ad[fine], k1);
+        const double c = c0n == 0.0 && k0 == 0 ? 0.0 : shifted(c0n, k0);
+        const ld mm = mismatch(c, a);
+        if (mm < bm) {
+          bm = mm;
+          best_c = c;
+          best_a = a;
+        }
+      }
+    c0d = best_c;
+    ad = best_a;
+  }
+  out.s = t.s;
+  out.nr = (int)real.size();
+  out.nb = nb;
+  out.nc = (int)cplx.size();
+  out.K = K;
+  out.NL = NL;
+  for (int i = 0; i < t.s; ++i)
+    for (int j = 0; j < t.s; ++j) out.A[i][j] = t.A[i][j];
+  out.inv_gamma = (double)(1.0L / gl);
+  out.c0 = c0d;
+  for (int i = 0; i < nt; ++i) {
+    PfTermDev& f = out.t[i];
+    f.dir = terms[i].dir;
+    f.q[0] = qd[2 * i];
+    f.q[1] = qd[2 * i + 1];
+    f.a[0] = ad[2 * i];
+    f.a[1] = ad[2 * i + 1];
+    // chunk factor Q = q^K and its powers, from the FP64 q, in extended
+    // precision
+    const cld q((ld)f.q[0], (ld)f.q[1]);
+    cld Q = 1.0L;
+    for (int k = 0; k < K; ++k) Q *= q;
+    cld pw = Q;
+    for (int d = 0; d < 11; ++d) {
+      f.Qp[d][0] = (double)pw.real();
+      f.Qp[d][1] = (double)pw.imag();
+      pw *= pw;
+    }
+    cld QN = 1.0L;
+    for (int l = 0; l < NL; ++l) QN *= Q;
+    const cld cl = 1.0L / (1.0L - QN);
+    f.close[0] = (double)cl.real();
+    f.close[1] = (double)cl.imag();
+  }
+  return true;
+}
+
 }  // namespace mgr

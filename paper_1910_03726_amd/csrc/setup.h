@@ -98,6 +98,13 @@ double inflow_entry(const InflowOp& op, int nx, int i, int c);
 
 // SDIRK: factor M = I - gamma dt L into cyclic recurrences (see common.h)
 // and fill the stage data; scan constants for chunk K and NL lanes.
+// The partial-fraction form (SdirkPfDev): false, with err set, when the
+// stage matrix has a repeated or nearly repeated root (the terms would
+// cancel: sum |terms| above 64 |M^{-1}| on some wave) or more than
+// MAX_PF_TERMS terms; the factored form then applies.
+bool sdirk_setup_pf(const Tableau& t, double cfl, int K, int NL, SdirkPfDev& out,
+                    std::string& err);
+
 bool sdirk_setup(const Tableau& t, double cfl, int K, int NL, SdirkDev& out,
                  std::string& err);
 

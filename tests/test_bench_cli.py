@@ -23,7 +23,7 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.parametrize("workload,source", [
     ("erk5_u5_nx8192_nt65536_m8_fp32relax", "relax_kernels.h"),
     ("erk3_u3_nx4096_nt16384_m8_fcycle", "relax_kernels.h"),
-    ("sdirk3_u3_nx2048_nt8192_m16_2level", "sdirk_kernels.h"),
+    ("sdirk3_u3_nx2048_nt8192_m16_2level", "sdirk_pf_kernels.h"),
     ("erk3_u3_inflow_nx4096_nt16384_m8_vcycle", "bounded_kernels.h"),
 ])
 def test_committed_counters_match_the_kernel_sources(workload, source):
