@@ -721,7 +721,12 @@ int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride
   }
   const int grid = L.nc + (mode == MODE_F ? 1 : 0);
   if (l == 0) fine_dof_steps += (double)L.nc * steps * nx;
-  if (profiling) tag = relax_tag(op, a, grid, l, prec);
+  if (profiling) {
+    tag = relax_tag(op, a, grid, l, prec);
+    // on coarse levels a homogeneous FC pass is the residual's propagation
+    // of the FCF update (cycle() in solve.cpp)
+    if (l > 0 && mode == MODE_FC && !rhs) tag.pass = MGRIT_PASS_RES;
+  }
   return launch(op, prec, a, grid, l == 0 ? MGRIT_PROF_RELAX_FINE
                                           : (mode == MODE_F ? MGRIT_PROF_OTHER
                                                             : MGRIT_PROF_RELAX_COARSE));

@@ -183,6 +183,13 @@ void coarse_solve(Group& G, const List& l0, int l, int kind, int prec) {
 
 // One V- or F-cycle on level l >= 1 (Sec. 4.4): relax, residual, coarse
 // solve, correct + F-relax.  Guess: lev[l].X (all points) unless `zero`.
+//
+// With FCF the C-point residual needs no right-hand side rows: the FC pass
+// gives v_{j+1} = Psi^m x_j + h_j (h_j the interval's propagated right-hand
+// side), so r_{j+1} = Psi^m v_j + h_j - v_{j+1} = Psi^m (v_j - x_j).  The FC
+// pass also writes the update d = v - x, and the residual pass propagates d
+// alone: m right-hand side rows per interval less to read.  d is held in
+// lev[l+1].X, which the coarse solve overwrites only afterwards.
 void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec) {
   List a = live(l0);
   for (Member* M : a) {
@@ -191,7 +198,7 @@ void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec) {
     const double* guess = zero ? nullptr : L.X;
     if (P->relax_kind == MGRIT_RELAX_FCF)
       Group::check(M, P->relax(l, prec, MODE_FC, guess, P->m, nullptr, rhs_of(M, l), RHS_EVERY,
-                               L.V, nullptr, P->m));
+                               L.V, nullptr, P->m, P->lev[l + 1].X));
     else  // F-relaxation only: v = u
       Group::check(M, P->copy_cpoints(l, prec, guess, P->m, nullptr, L.V));
   }
@@ -200,8 +207,12 @@ void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec) {
   for (Member* M : a) {
     Plan* P = M->P;
     Level& L = P->lev[l];
-    Group::check(M, P->relax(l, prec, MODE_RES, L.V, 1, nullptr, rhs_of(M, l), RHS_EVERY, L.R,
-                             nullptr, P->m));
+    if (P->relax_kind == MGRIT_RELAX_FCF)
+      Group::check(M, P->relax(l, prec, MODE_FC, P->lev[l + 1].X, 1, nullptr, nullptr, RHS_NONE,
+                               L.R, nullptr, P->m));
+    else
+      Group::check(M, P->relax(l, prec, MODE_RES, L.V, 1, nullptr, rhs_of(M, l), RHS_EVERY, L.R,
+                               nullptr, P->m));
   }
   G.flush(a);
   coarse_solve(G, a, l + 1, kind, prec);
