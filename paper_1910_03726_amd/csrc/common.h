@@ -38,6 +38,8 @@ struct RelaxArgs {
   long long in_stride;     // in rows
   const double* corr;
   long long corr_stride;   // in rows
+  const double* sub;       // may be null: also subtract sub[j] and sub2[j]
+  const double* sub2;      // (rows of n_x, stride 1) from the start state
   const double* rhs;
   const double* ref;       // MODE_RES: the C-points v being tested
   double* out;

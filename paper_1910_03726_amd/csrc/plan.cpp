@@ -679,6 +679,8 @@ static ProfTag relax_tag(const OpDesc& op, const RelaxArgs& a, int grid, int lev
   double rows = 0.0;
   if (!a.zero_in) rows += grid;
   if (a.corr) rows += grid;
+  if (a.sub) rows += grid;
+  if (a.sub2) rows += grid;
   if (a.rhs_mode == RHS_EVERY) rows += nint * m;
   if (a.rhs_mode == RHS_CPOINT) rows += nint;
   if (a.mode == MODE_FC) {
@@ -697,7 +699,8 @@ static ProfTag relax_tag(const OpDesc& op, const RelaxArgs& a, int grid, int lev
 // Relaxation on level l (0 = fine).  mode: MODE_FC / MODE_RES / MODE_F.
 int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride,
                 const double* corr, const double* rhs, int rhs_mode, double* out,
-                double* partial, int steps, double* delta) {
+                double* partial, int steps, double* delta, const double* sub,
+                const double* sub2) {
   Level& L = lev[l];
   const OpDesc& op = L.op;
   RelaxArgs a = base_args(*this, op);
@@ -705,6 +708,8 @@ int Plan::relax(int l, int prec, int mode, const double* in, long long in_stride
   a.in_stride = in_stride;
   a.zero_in = in == nullptr;
   a.corr = corr;
+  a.sub = sub;
+  a.sub2 = sub2;
   a.rhs = rhs;
   a.rhs_mode = rhs ? rhs_mode : RHS_NONE;
   a.mode = mode;

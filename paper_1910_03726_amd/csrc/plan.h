@@ -185,7 +185,8 @@ struct Plan {
   void end_util(int cls, hipEvent_t e0);
   int relax(int l, int prec, int mode, const double* in, long long in_stride,
             const double* corr, const double* rhs, int rhs_mode, double* out,
-            double* partial, int steps, double* delta = nullptr);
+            double* partial, int steps, double* delta = nullptr,
+            const double* sub = nullptr, const double* sub2 = nullptr);
   int copy_cpoints(int l, int prec, const double* in, long long in_stride,
                    const double* corr, double* out);
   // one launch of the coarsest level's sequential sweep (steps s0..), or 1

@@ -161,6 +161,18 @@ __device__ __forceinline__ void start_state(const RelaxArgs& a, int j, const Sta
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] += c[k];
   }
+  if (a.sub) {
+    double c[K];
+    S.load(a.sub + (long long)j * a.nx, 0, c);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] -= c[k];
+  }
+  if (a.sub2) {
+    double c[K];
+    S.load(a.sub2 + (long long)j * a.nx, 0, c);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] -= c[k];
+  }
 }
 
 // Stores after the last step; `sh` is the frame shift of x.
@@ -407,6 +419,20 @@ __device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) 
 #pragma unroll
         for (int q = 0; q < K; ++q) v[q] += cr[q];
       }
+      // one row at a time, like the correction, so that at most one row
+      // beside v is held in registers
+      if (a.sub) {
+        double sr[K];
+        X.fetch(a.sub + (long long)j * nx, 0, sr);
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] -= sr[q];
+      }
+      if (a.sub2) {
+        double sr[K];
+        X.fetch(a.sub2 + (long long)j * nx, 0, sr);
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] -= sr[q];
+      }
     }
     X.put(stg, v);
   }
@@ -636,6 +662,8 @@ __device__ __forceinline__ void generic_body(const RelaxArgs& a, const int j) {
     if (!a.zero_in) {
       v = a.in[(long long)j * a.in_stride * nx + p];
       if (a.corr) v += a.corr[(long long)j * a.corr_stride * nx + p];
+      if (a.sub) v -= a.sub[(long long)j * nx + p];
+      if (a.sub2) v -= a.sub2[(long long)j * nx + p];
     }
     if (a.mode == MODE_F) a.out[(long long)j * m * nx + p] = v;
     else if (a.mode == MODE_FC && a.write_row0 && j == 0) a.out[p] = v;

@@ -290,10 +290,10 @@ void judge(Member* M, int idx) {
 // the FP64 solver is v = FC(u) and its residual r_{j+1} = Phi^m v_j -
 // v_{j+1}.  Writing v = u + d (d the C-relaxation update, d^0 = 0) gives
 // exactly r_{j+1} = Phi^m d_j, because Phi^m u_j = v_{j+1}: the second fine
-// pass acts only on the small update d and runs in FP32 with errors
-// relative to |d|, while the C-point iterate, its FC pass, the coarse
-// correction and the norms stay FP64.  Iteration by iteration this is the
-// FP64 solver.
+// pass acts only on the small update d -- formed in FP64 from v, cur and
+// corr as it starts -- and runs in FP32 with errors relative to |d|, while
+// the C-point iterate, its FC pass, the coarse correction and the norms
+// stay FP64.  Iteration by iteration this is the FP64 solver.
 void solve_plain(Group& G, const List& all, bool mixed) {
   for (Member* M : all) {
     Plan* P = M->P;
@@ -307,11 +307,7 @@ void solve_plain(Group& G, const List& all, bool mixed) {
     if (a.empty()) break;
     for (Member* M : a) {
       Plan* P = M->P;
-      if (mixed) {
-        Group::check(M, P->relax(0, 0, MODE_FC, M->cur, 1, M->corr, nullptr, RHS_NONE, M->nxt,
-                                 nullptr, P->m, P->U));
-        P->stats.fine_passes_fp64 += 1;
-      } else if (P->relax_kind == MGRIT_RELAX_FCF) {
+      if (mixed || P->relax_kind == MGRIT_RELAX_FCF) {
         Group::check(M, P->relax(0, 0, MODE_FC, M->cur, 1, M->corr, nullptr, RHS_NONE, M->nxt,
                                  nullptr, P->m));
         P->stats.fine_passes_fp64 += 1;
@@ -324,8 +320,9 @@ void solve_plain(Group& G, const List& all, bool mixed) {
     for (Member* M : a) {
       Plan* P = M->P;
       if (mixed) {
-        Group::check(M, P->relax(0, 1, MODE_FC, P->U, 1, nullptr, nullptr, RHS_NONE,
-                                 P->lev[0].R, P->partial, P->m));
+        // r = Phi^m d with d = v - (cur + corr) formed at the start
+        Group::check(M, P->relax(0, 1, MODE_FC, M->nxt, 1, nullptr, nullptr, RHS_NONE,
+                                 P->lev[0].R, P->partial, P->m, nullptr, M->cur, M->corr));
         P->stats.fine_passes_fp32 += 1;
       } else {
         Group::check(M, P->relax(0, 0, MODE_RES, M->nxt, 1, nullptr, nullptr, RHS_NONE,
