@@ -140,7 +140,7 @@ def measured_traffic(workload, source):
 
 def _kernel_source(w):
     if w.get("boundary") == "inflow":
-        return "bounded_kernels.h", "k_bounded_tiled"
+        return "bounded_kernels.h", "k_bounded_reg"
     if w["scheme"].startswith("SDIRK"):
         return "sdirk_pf_kernels.h", "k_sdirk_pf"
     return "relax_kernels.h", "k_stencil"

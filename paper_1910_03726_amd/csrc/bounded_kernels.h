@@ -362,6 +362,328 @@ __global__ void __launch_bounds__(256) k_bounded_b(BatchArgs b) {
   bounded_body(a, blk);
 }
 
+// For lane l < 63 the value v of lane l + 1 of the wavefront, for lane 63
+// `old` (DPP wave_shl:1 without bound control).
+__device__ __forceinline__ double shl1(double old, double v) {
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x130, 0xf,
+                                             0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x130, 0xf,
+                                             0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Lane-resident variant for the fine level: one interval per workgroup.
+// Lanes 0..NL-1 (NL = blockDim.x - 64) own K consecutive points each in
+// registers, lane l the points l*K .. l*K+K-1 (points from n_x on are
+// zeros); the stencil is a dense window: out_p = sum_i c[i] u_{p-HL+i}, HL
+// points upwind and HR downwind.  A step takes the halos from the neighbour
+// lanes by DPP lane shifts and, at wavefront edges, from two LDS slots per
+// wavefront; one LDS-only barrier per step, and no global memory access
+// inside the step loop (with MODE_F the states are stored).
+//
+// The boundary rows are no stencil rows: lanes [0, a) and [b, nla) (the
+// chunks that hold them; `region` lanes) hand their points to the last
+// wavefront, which keeps those points' states in LDS (bu) and advances them
+// row by row, each row a dense window of the level's Phi (the closures of
+// Sec. 4.5 and, between them and the interior, stencil rows; at most
+// kRegLen weights, held in registers) over bu.  bu
+// holds, per step parity, the left region's points, lane a's chunk, lane
+// b-1's chunk and the right region's points; lanes a and b-1 export their
+// chunks there before the barrier.  After the barrier region lanes take
+// their points of the step from bu (their own stencil results are
+// discarded) before the DPP shifts, so every non-region lane reads true
+// values; a and b are no multiples of 64, so a region lane never feeds a
+// non-region lane through a wavefront-edge slot.  The inflow forcing (rows
+// < nf <= a*K) is added there too, staged in LDS before the first step (in
+// blocks of kRegFCap / nf steps when m * nf exceeds kRegFCap).  The two
+// kinds of wavefront run loops of their own with the same barriers.
+//
+// Modes FC (no update rows), RES and F, no right-hand side: the fine
+// level's passes; the host refuses the rest.
+//
+// LDS: the staging area NL*(K+1) doubles (start and end rows, coalesced),
+// the edge slots 2 * NL/64 * (HL+HR), bu 2 * rg_bu, the forcing kRegFCap:
+// under 40 KB for n_x = 4096, four workgroups per CU.
+template <int K, int HL, int HR>
+__device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j) {
+  constexpr int W = HL + HR + 1;
+  constexpr int HE = HL + HR;  // doubles of one wavefront's edge slots
+  constexpr int XB = kRegExportB<K, HL>();
+  constexpr int BL = 13;       // loads per thread in flight (row traffic):
+                               // one round trip per row for n_x = 4096
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  const BoundedDev* bd = reinterpret_cast<const BoundedDev*>(a.opdata);
+  const int nx = a.nx, m = a.m, NT = blockDim.x, tid = threadIdx.x;
+  const int NL = NT - 64, nwi = NL >> 6, lw = tid & 63;
+  // the wavefront index as a scalar: branches on it are uniform
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool bwave = wave >= nwi;
+  const int BU = bd->rg_bu;
+  const int np = NL * K;
+  double* stg = reinterpret_cast<double*>(smem_raw);
+  double* ed = stg + NL * (K + 1);
+  double* bu = ed + 2 * nwi * HE;
+  double* fst = bu + 2 * BU;
+  const int nf = bd->nf;
+  const double* const Fg = bd->F;
+  // forcing steps staged in LDS at a time
+  const int fr = nf > 0 ? kRegFCap / nf : 1;
+  const bool store_steps = a.mode == MODE_F;
+  const long long row0 = (long long)j * m;
+
+  // start state, staged (coalesced reads, then each lane its chunk); the
+  // last wavefront also stages the region rows, clears bu and stages the
+  // first forcing block
+  {
+    const double* in = a.zero_in ? nullptr : a.in + (long long)j * a.in_stride * nx;
+    const double* co =
+        (a.zero_in || !a.corr) ? nullptr : a.corr + (long long)j * a.corr_stride * nx;
+    const bool st0 = (a.mode == MODE_F && !a.skip_row0) ||
+                     (a.mode == MODE_FC && a.write_row0 && j == 0);
+    double* o0 = st0 ? a.out + (a.mode == MODE_F ? row0 * nx : 0LL) : nullptr;
+    for (int q0 = tid; q0 < np; q0 += BL * NT) {
+      double v[BL], c2[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = q0 + u * NT;
+        v[u] = (in && p < nx) ? in[p] : 0.0;
+        c2[u] = (co && p < nx) ? co[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = q0 + u * NT;
+        if (p < np) {
+          const double x = v[u] + c2[u];
+          if (o0 && p < nx) o0[p] = x;
+          stg[p + p / K] = x;
+        }
+      }
+    }
+    if (bwave) {
+      for (int q = lw; q < 2 * BU; q += 64) bu[q] = 0.0;
+      if (Fg && j < a.nint) {
+        const double* F0 = Fg + (long long)j * a.omin * nf;
+        const int n0 = min(fr, m) * nf;
+        for (int q = lw; q < n0; q += 64) fst[q] = F0[q];
+      }
+    }
+  }
+  if (a.mode == MODE_F && j == a.nint) return;  // extra block: the last C-point
+  __syncthreads();
+  const int ra = bd->rg_a, rb = bd->rg_b, nla = bd->rg_nla, LW = bd->rg_lw;
+  double x[K];
+
+  if (!bwave) {
+    // ---- lanes -----------------------------------------------------------
+    // bu slot of this lane's region points (-1: not a region lane, -2: zeros
+    // past the last chunk); lanes a and b-1 export their chunks
+    const int pslot =
+        tid < ra ? tid * K : (tid >= rb ? (tid < nla ? LW + (tid - rb + 1) * K : -2) : -1);
+    double c[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) c[i] = a.taps[i];
+    const int eo = wave * HE;
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = stg[tid * (K + 1) + k];
+    for (int s = 0; s < m; ++s) {
+      const int par = s & 1;
+      double* bcur = bu + par * BU;
+      double* ecur = ed + par * nwi * HE;
+      // exports of state s: wavefront edges, lanes a and b-1 (the last
+      // wavefront reads HR values of lane a, at most XB of lane b-1)
+      if (lw == 63) {
+#pragma unroll
+        for (int h = 0; h < HL; ++h) ecur[eo + h] = x[K - HL + h];
+      }
+      if (lw == 0) {
+#pragma unroll
+        for (int h = 0; h < HR; ++h) ecur[eo + HL + h] = x[h];
+      }
+      if (tid == ra) {
+#pragma unroll
+        for (int k = 0; k < HR; ++k) bcur[ra * K + k] = x[k];
+      }
+      if (tid == rb - 1) {
+#pragma unroll
+        for (int k = K - XB; k < K; ++k) bcur[LW + k] = x[k];
+      }
+      lds_barrier();
+      // region lanes: the true points of state s
+      if (pslot != -1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = pslot >= 0 ? bcur[pslot + k] : 0.0;
+      }
+      if (store_steps && s >= 1) {
+        double* orow = a.out + (row0 + s) * nx;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (tid * K + k < nx) orow[tid * K + k] = x[k];
+      }
+      double el[HL > 0 ? HL : 1], er[HR > 0 ? HR : 1];
+#pragma unroll
+      for (int h = 0; h < HL; ++h) el[h] = 0.0;
+#pragma unroll
+      for (int h = 0; h < HR; ++h) er[h] = 0.0;
+      if (wave > 0) {
+#pragma unroll
+        for (int h = 0; h < HL; ++h) el[h] = ecur[eo - HE + h];
+      }
+      if (wave + 1 < nwi) {
+#pragma unroll
+        for (int h = 0; h < HR; ++h) er[h] = ecur[eo + HE + HL + h];
+      }
+      double hl[HL > 0 ? HL : 1], hr[HR > 0 ? HR : 1];
+#pragma unroll
+      for (int h = 0; h < HL; ++h) hl[h] = shr1(el[h], x[K - HL + h]);
+#pragma unroll
+      for (int h = 0; h < HR; ++h) hr[h] = shl1(er[h], x[h]);
+      // in place, left to right: x[k] is overwritten by output k, its old
+      // value kept for outputs k+1..k+HL in a ring of HL registers
+      constexpr int HLa = HL > 0 ? HL : 1;
+      double old[HLa];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const int q = k - HL + i;
+          double u;
+          if (q < 0)
+            u = hl[q < 0 ? q + HL : 0];
+          else if (q < k)
+            u = old[q % HLa];
+          else if (q < K)
+            u = x[q < K ? q : 0];
+          else
+            u = hr[q >= K ? q - K : 0];
+          acc = fma(c[i], u, acc);
+        }
+        if constexpr (HL > 0) old[k % HLa] = x[k];
+        x[k] = acc;
+      }
+    }
+    lds_barrier();
+    if (pslot != -1) {
+      const double* bcur = bu + (m & 1) * BU;
+#pragma unroll
+      for (int k = 0; k < K; ++k) x[k] = pslot >= 0 ? bcur[pslot + k] : 0.0;
+    }
+    if (store_steps && m >= 1 && a.write_last) {
+      double* orow = a.out + (row0 + m) * nx;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (tid * K + k < nx) orow[tid * K + k] = x[k];
+    }
+    if (a.mode == MODE_FC || a.mode == MODE_RES) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) stg[tid * (K + 1) + k] = x[k];
+    }
+  } else {
+    // ---- the last wavefront: region row lw (< rg_rows) of point rp, a
+    // window of kRegLen weights (in registers) over bu from rcs, the result
+    // to slot rdst ----
+    const bool act = lw < bd->rg_rows;
+    int rcs = 0, rdst = 0, rp = nx;
+    double cr[kRegLen];
+#pragma unroll
+    for (int t = 0; t < kRegLen; ++t) cr[t] = 0.0;
+    if (act) {
+      rcs = bd->rg_cs[lw];
+      rdst = bd->rg_dst[lw];
+      rp = lw < ra * K ? lw : rb * K + (lw - ra * K);
+      const double* co = bd->rg_coef + lw * bd->rg_ls;
+#pragma unroll
+      for (int t = 0; t < kRegLen; ++t) cr[t] = co[t];
+    }
+    const bool rforce = act && Fg && rp < nf;
+    for (int q = lw; q < ra * K; q += 64) bu[q] = stg[q + q / K];
+    for (int q = lw; q < (nla - rb) * K; q += 64) {
+      const int p = rb * K + q;
+      bu[LW + K + q] = stg[p + p / K];
+    }
+    for (int s = 0; s < m; ++s) {
+      const int par = s & 1;
+      if (Fg && s > 0 && s % fr == 0) {
+        // the next block of forcing steps (m * nf > kRegFCap only)
+        const double* Fs = Fg + ((long long)j * a.omin + s) * nf;
+        const int n = min(fr, m - s) * nf;
+        for (int q = lw; q < n; q += 64) fst[q] = Fs[q];
+      }
+      lds_barrier();
+      if (act) {
+        const double* ur = bu + par * BU + rcs;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        // in two halves: at most half the window's reads in registers
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int t = h * kRegLen / 2; t < (h + 1) * kRegLen / 2; t += 4) {
+            s0 = fma(cr[t], ur[t], s0);
+            s1 = fma(cr[t + 1], ur[t + 1], s1);
+            s2 = fma(cr[t + 2], ur[t + 2], s2);
+            s3 = fma(cr[t + 3], ur[t + 3], s3);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        double v = (s0 + s1) + (s2 + s3);
+        if (rforce) v += fst[(s % fr) * nf + rp];
+        bu[(par ^ 1) * BU + rdst] = v;
+      }
+    }
+    lds_barrier();
+  }
+  if (a.mode != MODE_FC && a.mode != MODE_RES) return;
+  // final state through the staging area, then coalesced row work
+  __syncthreads();
+  double ss = 0.0;
+  if (a.mode == MODE_FC) {
+    double* orow = a.out + (long long)(j + a.out_off) * nx;
+    for (int p = tid; p < nx; p += NT) {
+      const double v = stg[p + p / K];
+      orow[p] = v;
+      ss += v * v;
+    }
+  } else {
+    const double* ref = a.ref + (long long)(j + 1) * nx;
+    double* orow = a.out + (long long)(j + 1) * nx;
+    for (int p0 = tid; p0 < nx; p0 += BL * NT) {
+      double rv[BL];
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        rv[u] = p < nx ? ref[p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < BL; ++u) {
+        const int p = p0 + u * NT;
+        if (p < nx) {
+          const double v = stg[p + p / K] - rv[u];
+          orow[p] = v;
+          if (j == 0) a.out[p] = 0.0;
+          ss += v * v;
+        }
+      }
+    }
+  }
+  if (a.partial) {
+    const double t = block_sum(ss, red);
+    if (tid == 0) a.partial[j] = t;
+  }
+}
+
+template <int K, int HL, int HR>
+__global__ void __launch_bounds__(1024, 5) k_bounded_reg(RelaxArgs a) {
+  bounded_reg_body<K, HL, HR>(a, (int)blockIdx.x);
+}
+
+template <int K, int HL, int HR>
+__global__ void __launch_bounds__(1024, 5) k_bounded_reg_b(BatchArgs b) {
+  int blk;
+  const RelaxArgs a = batch_member(b, blk);
+  bounded_reg_body<K, HL, HR>(a, blk);
+}
+
 template <int K, int W, bool PF>
 __global__ void __launch_bounds__(512) k_bounded_tiled(RelaxArgs a) {
   bounded_tiled_body<K, W, PF>(a, (int)blockIdx.x);

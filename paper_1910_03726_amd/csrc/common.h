@@ -73,6 +73,16 @@ struct RelaxArgs {
                            // rows staged in LDS before the first step
 };
 
+// Inflow forcing values (steps x nf) the lane-resident bounded kernel stages
+// in LDS at a time.
+constexpr int kRegFCap = 256;
+// Weights of one boundary row of that kernel (a multiple of 4).
+constexpr int kRegLen = 24;
+// The trailing values of lane b-1's chunk the right boundary rows may read:
+// the stencil's upwind reach and the outflow extrapolation's (at most 4).
+template <int K, int HL>
+constexpr int kRegExportB() { return HL + 4 < K ? HL + 4 : K; }
+
 // Several relaxation launches of the same kernel and launch shape merged
 // into one grid (requests served together): member i owns blocks
 // start[i] .. start[i+1]-1 (start[0] = 0) and runs with a[i] as if it had
@@ -101,6 +111,16 @@ struct BoundedDev {
   const double* lblk;
   const double* rblk;
   const double* F;
+  // lane-resident fine-level kernel (k_bounded_reg): region lanes [0, rg_a)
+  // and [rg_b, rg_nla) of K points; the LDS window bu of rg_bu doubles per
+  // step parity (left region and lane a's chunk in [0, rg_lw), then lane
+  // b-1's chunk and the right region); rg_rows region rows, row r a window
+  // of rg_len weights (rg_coef[r * rg_ls ..]) over bu from rg_cs[r], its
+  // result stored at bu slot rg_dst[r]
+  int rg_a, rg_b, rg_nla, rg_lw, rg_bu, rg_ls, rg_len, rg_rows;
+  const double* rg_coef;
+  const int* rg_cs;
+  const int* rg_dst;
 };
 
 // One factor of a cyclic banded stage solve: a linear recurrence of order

@@ -12,7 +12,21 @@ static void reg_tiled(KernelTable& t, int i) {
   t.bounded_tiled_b[1][i] = &k_bounded_tiled_b<bounded_k(W), W, true>;
 }
 
+template <int I>
+static void reg_lanes(KernelTable& t) {
+  constexpr int K = kBoundedReg[I][0], HL = kBoundedReg[I][1], HR = kBoundedReg[I][2];
+  t.bounded_reg[I] = &k_bounded_reg<K, HL, HR>;
+  t.bounded_reg_b[I] = &k_bounded_reg_b<K, HL, HR>;
+}
+
 void register_bounded(KernelTable& t) {
+  reg_lanes<0>(t);
+  reg_lanes<1>(t);
+  reg_lanes<2>(t);
+  reg_lanes<3>(t);
+  reg_lanes<4>(t);
+  reg_lanes<5>(t);
+  static_assert(kNumBoundedReg == 6, "");
   t.bounded = &k_bounded;
   t.bounded_b = &k_bounded_b;
   reg_tiled<4>(t, 0);

@@ -389,6 +389,98 @@ int OpDesc::init_sdirk(const Tableau& t, double cfl, int nx, std::string& err) {
   return upload(&d_sdirk, &sd, sizeof(SdirkDev));
 }
 
+// Region tables of the lane-resident fine-level kernel (k_bounded_reg,
+// bounded_kernels.h) for entry `inst` of kBoundedReg: false if the window
+// [omn, omx] of the interior stencil or the boundary rows do not fit it.
+struct RegRegion {
+  int K = 0, HL = 0, HR = 0, NT = 0;
+  int a = 0, b = 0, nla = 0, lw = 0, bu = 0, ls = 0, len = 0, rows = 0;
+  std::vector<double> coef;
+  std::vector<int> cs, dst;
+  size_t lds = 0;
+};
+
+static bool bounded_reg_region(const InflowOp& f, int nf, int nx, int inst, int omx, int omn,
+                               RegRegion& R) {
+  const int K = kBoundedReg[inst][0], HL = kBoundedReg[inst][1], HR = kBoundedReg[inst][2];
+  if (omx > HL || -omn > HR || f.nl < 1 || f.nr < 1) return false;
+  const int nla = (nx + K - 1) / K, NL = (nla + 63) / 64 * 64;
+  if (NL + 64 > 1024) return false;
+  // region lanes: [0, a) hold the left boundary rows, [b, nla) the right
+  // ones; lanes a-1 and a (b-1 and b) share a wavefront
+  int a = (f.nl + K - 1) / K;
+  if (a % 64 == 0) ++a;
+  int b = (nx - f.nr) / K;
+  if (b % 64 == 0) --b;
+  if (b <= a || nf > a * K) return false;
+  const int rows = a * K + (nla - b) * K;
+  if (rows > 64) return false;
+  const int LW = (a + 1) * K, RW = (nla - b + 1) * K;
+  // row r: point p; its nonzero columns and their bu slots
+  std::vector<int> mn(rows), mx(rows);
+  int len = 1;
+  for (int r = 0; r < rows; ++r) {
+    const int p = r < a * K ? r : b * K + (r - a * K);
+    int lo = 1 << 30, hi = -1;
+    if (p < nx) {
+      int c0, c1;
+      if (p < f.nl) {
+        c0 = 0;
+        c1 = f.ncl - 1;
+      } else if (p >= nx - f.nr) {
+        c0 = nx - f.ncr;
+        c1 = nx - 1;
+      } else {
+        c0 = std::max(0, p - omx);
+        c1 = std::min(nx - 1, p - omn);
+      }
+      for (int c = c0; c <= c1; ++c)
+        if (inflow_entry(f, nx, p, c) != 0.0) {
+          lo = std::min(lo, c);
+          hi = std::max(hi, c);
+        }
+    }
+    if (hi < 0) lo = hi = r < a * K ? 0 : b * K;  // a zero row
+    // lane a exports its first HR values, lane b-1 its last XB
+    const int XB = std::min(K, HL + 4);
+    if (r < a * K ? hi >= a * K + HR : lo < b * K - XB) return false;
+    mn[r] = lo;
+    mx[r] = hi;
+    len = std::max(len, hi - lo + 1);
+  }
+  len = (len + 3) / 4 * 4;
+  if (len > kRegLen) return false;
+  len = kRegLen;  // the kernel reads kRegLen weights (zeros past the row)
+  R.K = K;
+  R.HL = HL;
+  R.HR = HR;
+  R.NT = NL + 64;
+  R.a = a;
+  R.b = b;
+  R.nla = nla;
+  R.lw = LW;
+  R.bu = LW + RW + len;
+  R.len = len;
+  R.ls = len + 1;
+  R.rows = rows;
+  R.coef.assign((size_t)rows * R.ls, 0.0);
+  R.cs.assign(rows, 0);
+  R.dst.assign(rows, 0);
+  for (int r = 0; r < rows; ++r) {
+    const bool left = r < a * K;
+    const int p = left ? r : b * K + (r - a * K);
+    const int slot0 = left ? 0 : LW - (b - 1) * K;  // bu slot of column c: c + slot0
+    R.cs[r] = mn[r] + slot0;
+    R.dst[r] = p + slot0;
+    if (p < nx)
+      for (int c = mn[r]; c <= mx[r]; ++c)
+        R.coef[(size_t)r * R.ls + (c - mn[r])] = inflow_entry(f, nx, p, c);
+  }
+  R.lds = sizeof(double) * ((size_t)NL * (K + 1) + (size_t)2 * (NL / 64) * (HL + HR) +
+                            (size_t)2 * R.bu + kRegFCap);
+  return true;
+}
+
 int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
                          const std::vector<double>* F, int nx, int stride, std::string& err) {
   const KernelTable& kt = kernel_table();
@@ -424,7 +516,39 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
                                     (size_t)kFRowsLds * fine->nf
                               : 0));
   const int pf = fine ? 0 : 1;  // coarse levels add a right-hand side row every step
-  if (nnz && wi >= 0 && kt.bounded_tiled[pf][wi] && 4 * nbrows <= 512 &&
+  // fine level: the lane-resident kernel, chunks of 16 points from n_x =
+  // 2048 on (else 8 where the halos fit), the smallest compiled window
+  RegRegion R;
+  bool lanes = false;
+  if (fine && nnz) {
+    const int nf = F ? fine->nf : 0;
+    for (int pass = 0; pass < 2 && !lanes; ++pass) {
+      const int Kw = (nx >= 2048) == (pass == 0) ? 16 : 8;
+      for (int i = 0; i < kNumBoundedReg && !lanes; ++i) {
+        if (kBoundedReg[i][0] != Kw || !kt.bounded_reg[i]) continue;
+        if (!bounded_reg_region(*fine, nf, nx, i, omx, omn, R)) continue;
+        if (R.lds > kernel_info(kt.bounded_reg[i]).max_lds || spills(kt.bounded_reg[i])) continue;
+        lanes = true;
+        reg_inst = i;
+      }
+    }
+  }
+  if (lanes) {
+    const int Wr = R.HL + R.HR + 1;
+    std::vector<double> dense(Wr, 0.0);
+    for (size_t t = 0; t < interior.off.size(); ++t) dense[R.HL - interior.off[t]] += interior.w[t];
+    fn[0] = kt.bounded_reg[reg_inst];
+    bfn[0] = kt.bounded_reg_b[reg_inst];
+    NL = R.NT;
+    K = R.K;
+    shmem[0] = shmem[1] = R.lds;
+    ntaps = Wr;
+    width = W;
+    Wbucket = 0;
+    reg_rows = R.rows;
+    rc = upload((void**)&d_taps, dense.data(), dense.size() * sizeof(double));
+    if (!rc) rc = upload((void**)&d_off, &R.HL, sizeof(int));
+  } else if (nnz && wi >= 0 && kt.bounded_tiled[pf][wi] && 4 * nbrows <= 512 &&
       tiled_lds <= kernel_info(kt.bounded_tiled[pf][wi]).max_lds) {
     const int Wb = kBoundedWidths[wi];
     std::vector<double> dense(Wb, 0.0);
@@ -481,6 +605,24 @@ int OpDesc::init_bounded(const Taps& interior, const InflowOp* fine,
     if ((rc = put(fine->lblk, &bd.lblk)) || (rc = put(fine->rblk, &bd.rblk))) return rc;
     if (bd.nf > 0 && (rc = put(*F, &bd.F))) return rc;
   }
+  if (lanes) {
+    bd.rg_a = R.a;
+    bd.rg_b = R.b;
+    bd.rg_nla = R.nla;
+    bd.rg_lw = R.lw;
+    bd.rg_bu = R.bu;
+    bd.rg_ls = R.ls;
+    bd.rg_len = R.len;
+    bd.rg_rows = R.rows;
+    if ((rc = put(R.coef, &bd.rg_coef))) return rc;
+    void* d = nullptr;
+    for (int t = 0; t < 2; ++t) {
+      const std::vector<int>& h = t ? R.dst : R.cs;
+      if ((rc = upload(&d, h.data(), h.size() * sizeof(int)))) return rc;
+      d_extra.push_back(d);
+      (t ? bd.rg_dst : bd.rg_cs) = (const int*)d;
+    }
+  }
   return upload(&d_bnd, &bd, sizeof bd);
 }
 
@@ -531,8 +673,11 @@ std::string OpDesc::describe() const {
     snprintf(buf, sizeof buf, "generic ntaps=%d NT=%d", ntaps, NL);
   else if (kind == OP_BOUNDED)
   {
-    char kw[32] = "", nq[32] = "";
+    char kw[64] = "", nq[32] = "";
     if (Wbucket) snprintf(kw, sizeof kw, "<K=%d,W=%d>", bounded_k(Wbucket), Wbucket);
+    if (reg_inst >= 0)
+      snprintf(kw, sizeof kw, "_lanes<K=%d,HL=%d,HR=%d> rows=%d", kBoundedReg[reg_inst][0],
+               kBoundedReg[reg_inst][1], kBoundedReg[reg_inst][2], reg_rows);
     if (nilq) snprintf(nq, sizeof nq, " nilpotent q=%d", nilq);
     snprintf(buf, sizeof buf, "bounded%s ntaps=%d NT=%d%s%s", kw, ntaps, NL,
              d_extra.empty() ? "" : " +boundary rows", nq);
@@ -593,6 +738,10 @@ int Plan::launch(const OpDesc& op, int prec, const RelaxArgs& a, int grid, int c
     parts = (int)blocks;
   }
   if (!fn || blocks < 1 || blocks > 0x7fffffffLL) return MGRIT_EINVAL;
+  // the lane-resident bounded kernel runs the fine level's passes only
+  if (op.reg_inst >= 0 &&
+      (a.rhs_mode != RHS_NONE || a.mode == MODE_FW || a.delta || a.sub || a.sub2))
+    return MGRIT_EINVAL;
   if (batch) {
     batch->pending.push_back({fn, bfn, nl, lds, blocks, args, this});
     return MGRIT_OK;

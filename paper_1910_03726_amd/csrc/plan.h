@@ -71,6 +71,8 @@ struct OpDesc {
   void* d_sdirk = nullptr;              // SDIRK: device SdirkPfDev (sdirk_terms > 0)
   int sdirk_terms = 0;                  // or SdirkDev (the factored form)
   void* d_bnd = nullptr;                // bounded kernel: device BoundedDev
+  int reg_inst = -1, reg_rows = 0;      // bounded fine level: kBoundedReg entry of
+                                        // the lane-resident kernel, its region rows
   int nilq = 0;                         // bounded coarse operator with every offset
                                         // >= 1: Psi^nilq = 0 (else 0)
   std::vector<void*> d_extra;           // bounded kernel: its blocks and forcing

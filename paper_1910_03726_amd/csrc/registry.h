@@ -49,6 +49,9 @@ struct KernelTable {
   // [right-hand side rows prefetched (coarse levels)][width]
   KernelFn bounded_tiled[2][8] = {};
   BatchFn bounded_tiled_b[2][8] = {};
+  // fine levels: points held in registers (K, HL, HR of kBoundedReg)
+  KernelFn bounded_reg[8] = {};
+  BatchFn bounded_reg_b[8] = {};
 };
 // points per thread chunk (any window width): odd, so lanes K doubles apart
 // hit distinct LDS banks
@@ -57,6 +60,13 @@ constexpr int bounded_k(int) { return 9; }
 constexpr int kFRowsLds = 64;
 constexpr int kNumBoundedWidths = 8;
 constexpr int kBoundedWidths[kNumBoundedWidths] = {4, 8, 12, 16, 24, 32, 48, 64};
+// lane-resident fine-level kernels: {K points per lane, HL upwind halo, HR
+// downwind halo}; the windows of ERKp+Up for p = 1..3 (wider windows need
+// more registers than three wavefronts per SIMD leave)
+constexpr int kNumBoundedReg = 6;
+constexpr int kBoundedReg[kNumBoundedReg][3] = {{8, 1, 0},  {8, 4, 0},  {8, 6, 3},
+                                                {16, 1, 0}, {16, 4, 0}, {16, 6, 3}};
+
 
 // Filled once on first use; prec 0 = FP64 state, 1 = FP32 state.
 const KernelTable& kernel_table();

@@ -58,6 +58,38 @@ def test_phi_apply_batch_steps_with_inflow_data():
             P.phi_apply_batch(x, out, nt + 1)  # beyond the inflow data
 
 
+LANE_CASES = [
+    # scheme, nx, the chunk size the plan picks
+    ("ERK1", 1003, 8),   # ragged last chunk
+    ("ERK2", 777, 8),
+    ("ERK3", 1040, 8),   # right region moved off a wavefront edge
+    ("ERK3", 2500, 16),  # several wavefronts, ragged
+    ("ERK1", 4096, 16),
+    ("ERK3", 4096, 16),
+]
+
+
+@pytest.mark.parametrize("case", LANE_CASES, ids=[f"{c[0]}-{c[1]}" for c in LANE_CASES])
+def test_lane_kernel_steps_like_the_oracle(case):
+    # the fine level's lane-resident kernel: k steps of the bounded Phi with
+    # the inflow forcing, from several start rows
+    s, nx, K = case
+    nt = 48
+    d, c, H, psi, G = _setup(s, nx, nt, 4, 2)
+    rows = np.stack([inputs.fourier_u0(nx, 4, k) for k in range(3)])
+    rows[1] = inputs.random_iterate(1, nx, 11)[0]
+    with M.Plan(nx, nt, c, s, 4, 2, psi, inflow=G) as P:
+        assert f"bounded_lanes<K={K}," in P.describe()
+        x = torch.tensor(rows, device="cuda")
+        out = torch.empty_like(x)
+        for k in (0, 1, 8, 37):
+            P.phi_apply_batch(x, out, k)
+            torch.cuda.synchronize()
+            ref = np.stack([d.time_stepping(r, G[:k], every=max(k, 1))[-1] for r in rows])
+            got = out.cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), (k, s, nx)
+
+
 CASES = [
     # scheme, nx, nt, m, levels, cycle, relax, widths
     ("ERK1", 256, 1024, 4, 2, "V", "FCF", [3]),
@@ -188,12 +220,14 @@ def test_wide_window_uses_the_point_kernel():
 
 
 def test_several_chunks_per_thread():
-    # n_x = 8192: more chunks than threads in the register-blocked kernel
+    # n_x = 8192: the fine level on the lane-resident kernel (512 lanes of
+    # 16 points), the coarse levels with more chunks than threads in the
+    # register-blocked kernel
     s, nx, nt, m, L = "ERK3", 8192, 512, 4, 3
     d, c, H, psi, G = _setup(s, nx, nt, m, L)
     u0 = np.sin(np.pi * (d.x + 1.0)) ** 4
     with M.Plan(nx, nt, c, s, m, L, psi, inflow=G) as P:
-        assert "bounded<K=" in P.describe()
+        assert "bounded<K=" in P.describe() and "bounded_lanes<K=16," in P.describe()
         r = P.solve(torch.tensor(u0, device="cuda"), None, tol=1e-12, maxit=60, out="final")
     assert r.status == M.OK
     ref = d.time_stepping(u0, G, every=nt)[-1]
