@@ -414,6 +414,14 @@ def main():
             "speedup_median": round(r64["step_ms"]["median"] / rec["step_ms"]["median"], 4),
             "spread_fp32": round(rec["step_ms"]["p95"] / rec["step_ms"]["median"] - 1, 4),
             "spread_fp64": round(r64["step_ms"]["p95"] / r64["step_ms"]["median"] - 1, 4)}
+        # the other FP32 form: every inner fine pass in FP32 inside FP64
+        # iterative refinement (the residual of the iterate in FP64)
+        Pir, _, _, rir, _, _, _ = solve_record(a.workload, w, max(5, steps // 2), a.warmup,
+                                               torch, "fp32_ir", ref)
+        Pir.close()
+        line["fp32_ir"] = rir
+        line["fp32_vs_fp64"]["speedup_median_ir"] = round(
+            r64["step_ms"]["median"] / rir["step_ms"]["median"], 4)
     extra = {}
     if w["psi_rule"] == "bound":  # the same solve with the Sec. 4.4 width rule
         ww = dict(w, psi_rule="window")

@@ -74,6 +74,10 @@ extern "C" {
                                 the second fine pass acts on the C-point
                                 update in FP32; with F-relaxation, FP32 inner
                                 cycles inside FP64 iterative refinement     */
+#define MGRIT_FP32_IR 2      /* FP32 inner cycles (both fine passes FP32,
+                                FCF or F) inside FP64 iterative refinement:
+                                FP64 residual of the iterate, inner solve of
+                                the error system, FP64 update              */
 
 /* coarse-operator pattern rules for mgrit_psi_optimize */
 #define MGRIT_PSI_AUTO 0     /* ETA for SDIRK, WINDOW for ERK                 */
@@ -104,7 +108,8 @@ typedef struct mgrit_plan_s* mgrit_plan_t;
 typedef struct {
     int iterations;        /* fine-level coarse-grid corrections applied      */
     int outer_iterations;  /* MGRIT_FP32_RELAX: FP64 fine passes (FCF) or
-                              FP64 refinement steps (F-relaxation), else 0 */
+                              FP64 refinement steps (F-relaxation);
+                              MGRIT_FP32_IR: FP64 refinement steps; else 0 */
     int fine_passes_fp64;  /* fine-level relaxation passes run in FP64        */
     int fine_passes_fp32;  /* fine-level relaxation passes run in FP32        */
     double final_residual; /* sqrt(dx dt sum r^2) of the returned iterate     */
@@ -262,8 +267,9 @@ int mgrit_inflow_operator(int scheme, double cfl, double alpha, int nx,
  *   maxit:     maximum coarse-grid corrections (>= 0).
  *   u_out_dev: output per out_kind (MGRIT_OUT_*), may be NULL for NONE.
  *   res_hist_host: may be NULL, else room for maxit+1 doubles: the
- *              residual norm before each correction (for MGRIT_FP32_RELAX
- *              with F-relaxation: the FP64 refinement residuals).
+ *              residual norm before each correction (for MGRIT_FP32_IR, and
+ *              MGRIT_FP32_RELAX with F-relaxation: the FP64 refinement
+ *              residuals).
  *   iters_out: may be NULL; receives the number of corrections.
  * Returns MGRIT_ENOTCONV if maxit is reached (outputs still written),
  * MGRIT_EDIVERGED on a non-finite norm.  Synchronous. */

@@ -1033,7 +1033,7 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
   const size_t row = (size_t)nx * sizeof(double);
   const long long nc = nt / m;
   size_t b = 3 * (size_t)(nc + 1) * row;                       // V_a, V_b, R_1
-  if (precision == MGRIT_FP32_RELAX) b += 2 * (size_t)(nc + 1) * row;  // U, R_out
+  if (precision != MGRIT_FP64) b += 2 * (size_t)(nc + 1) * row;  // U, R_out
   long long n = nt;
   for (int l = 1; l < levels; ++l) {
     n /= m;
@@ -1356,7 +1356,8 @@ static int plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double c
     return MGRIT_EINVAL;
   if (cycle != MGRIT_CYCLE_V && cycle != MGRIT_CYCLE_F) return MGRIT_EINVAL;
   if (relax != MGRIT_RELAX_FCF && relax != MGRIT_RELAX_F) return MGRIT_EINVAL;
-  if (precision != MGRIT_FP64 && precision != MGRIT_FP32_RELAX) return MGRIT_EINVAL;
+  if (precision != MGRIT_FP64 && precision != MGRIT_FP32_RELAX && precision != MGRIT_FP32_IR)
+    return MGRIT_EINVAL;
   long long span = 1;
   for (int l = 1; l < levels; ++l) span *= m;
   if (span > nt || nt % span) return MGRIT_EINVAL;
@@ -1449,7 +1450,7 @@ static int plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double c
     const long long nc = nt / m;
     if (!alloc(&P->Va, nc + 1) || !alloc(&P->Vb, nc + 1) || !alloc(&P->lev[0].R, nc + 1))
       return fail(MGRIT_ENOMEM);
-    if (precision == MGRIT_FP32_RELAX && (!alloc(&P->U, nc + 1) || !alloc(&P->Rout, nc + 1)))
+    if (precision != MGRIT_FP64 && (!alloc(&P->U, nc + 1) || !alloc(&P->Rout, nc + 1)))
       return fail(MGRIT_ENOMEM);
     for (int l = 1; l < levels; ++l) {
       Level& L = P->lev[l];
@@ -1691,7 +1692,7 @@ int phi_apply_batch(mgrit_plan_t plan, const double* in, double* out, int batch,
     if (ksteps > P->nt) return MGRIT_EINVAL;
     a.omin = 0;
   }
-  const int prec = P->precision == MGRIT_FP32_RELAX ? 1 : 0;
+  const int prec = P->precision != MGRIT_FP64 ? 1 : 0;
   if (P->profiling) P->tag = relax_tag(op, a, batch, 0, prec);
   return P->launch(op, prec, a, batch, MGRIT_PROF_RELAX_FINE);
 }

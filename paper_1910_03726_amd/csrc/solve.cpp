@@ -497,12 +497,14 @@ int solve_group(Plan* const* plans, int n, const double* const* u0, const double
   auto t0 = std::chrono::steady_clock::now();
   Group G(stream, n > 1);
   G.attach(all);
-  // members of one solve form: FP64, FP32 with FCF, FP32 with F-relaxation
+  // members of one solve form: FP64, FP32 with FCF (correction form), FP32
+  // iterative refinement (F-relaxation, or asked for)
   List plain, mixed, ir;
   for (Member* M : all) {
     const Plan* P = M->P;
-    if (P->precision != MGRIT_FP32_RELAX) plain.push_back(M);
-    else if (P->relax_kind == MGRIT_RELAX_FCF) mixed.push_back(M);
+    if (P->precision == MGRIT_FP64) plain.push_back(M);
+    else if (P->precision == MGRIT_FP32_RELAX && P->relax_kind == MGRIT_RELAX_FCF)
+      mixed.push_back(M);
     else ir.push_back(M);
   }
   if (!plain.empty()) solve_plain(G, plain, false);

@@ -20,7 +20,7 @@ SCHEMES = {"ERK1": 1, "ERK2": 2, "ERK3": 3, "ERK4": 4, "ERK5": 5,
            "SDIRK1": 11, "SDIRK2": 12, "SDIRK3": 13, "SDIRK4": 14}
 CYCLES = {"V": 0, "F": 1}
 RELAX = {"FCF": 0, "F": 1}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "fp32_ir": 2}
 PSI_RULES = {"auto": 0, "window": 1, "eta": 2, "redisc": 3}
 OUT = {"none": 0, "final": 1, "cpoints": 2, "all": 3}
 
@@ -428,9 +428,9 @@ class Plan:
 
     def _result(self, rc, iters, hist, u_out):
         st = self.stats()
-        # one norm per correction; FP32 Parareal (F-relaxation) records one
-        # per FP64 refinement step instead
-        refine = self.precision == "fp32" and self.relax == "F"
+        # one norm per correction; FP32 iterative refinement (asked for, or
+        # FP32 Parareal) records one per FP64 refinement step instead
+        refine = self.precision == "fp32_ir" or (self.precision == "fp32" and self.relax == "F")
         nh = (st.outer_iterations if refine else iters) + 1
         return SolveResult(rc, iters, list(hist[:nh]), u_out, st)
 

@@ -277,6 +277,28 @@ def test_fp32_relaxation_tracks_the_fp64_iteration(s, nx, nt, m, L, cycle):
     assert _rel(_n(g32.out), seq) < 1e-9
 
 
+@pytest.mark.parametrize("s,nx,nt,m,L,relax", [
+    ("ERK5", 256, 2048, 8, 3, "FCF"), ("SDIRK3", 256, 1024, 4, 2, "FCF"),
+    ("ERK3", 256, 1024, 4, 2, "F")])
+def test_fp32_iterative_refinement(s, nx, nt, m, L, relax):
+    # precision "fp32_ir": every fine pass of the inner cycles in FP32 (FCF
+    # or F), the residual of the iterate, the update and the norms in FP64;
+    # the refinement residuals fall to the FP64 tolerance and the iterate
+    # is the FP64 solution.
+    c = rk.paper_cfl(s) if s.startswith("ERK") else 4.0
+    d = rk.Discretization(s, nx, c)
+    psi = _oracle_hierarchy(d, m, L)
+    u0 = inputs.fourier_u0(nx, 8, 0)
+    with M.Plan(nx, nt, c, s, m, L, psi, relax=relax, precision="fp32_ir") as P:
+        g = P.solve(_t(u0), None, tol=1e-10, maxit=60, out="cpoints")
+        st = P.stats()
+    assert g.converged and g.hist[-1] <= 1e-10
+    assert len(g.hist) == st.outer_iterations + 1
+    assert all(b < a for a, b in zip(g.hist, g.hist[1:]))
+    assert st.fine_passes_fp32 > 0 and st.outer_iterations >= 1
+    assert _rel(_n(g.out), d.time_stepping(u0, nt, every=m)) < 1e-8
+
+
 def test_fp32_parareal_refinement():
     # F-relaxation with FP32 relaxation: FP32 inner cycles inside FP64
     # iterative refinement reach the FP64 solution.
