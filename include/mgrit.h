@@ -203,8 +203,10 @@ int mgrit_psi_optimize_bound(int scheme, double cfl, int nx, int nt, int m,
 
 /* ---- plans and solves (GPU) --------------------------------------------- */
 
-/* Create a plan for n_x, n_t, alpha, Courant number c, scheme, coarsening
- * factor m and `levels` >= 2 levels (n_t divisible by m^(levels-1); each
+/* Create a plan for the space-time system of eq. (3) (Sec. 2.2) and its
+ * MGRIT hierarchy (Sec. 4.4): n_x, n_t, alpha, Courant number c, scheme,
+ * coarsening factor m and `levels` >= 2 levels (n_t divisible by
+ * m^(levels-1); each
  * level has >= 2 coarse intervals).  psi: levels-1 coarse stencils
  * (Psi_2..Psi_levels), copied into the plan.  cycle/relax/precision: the
  * MGRIT_* options above.  hip_stream: a hipStream_t (NULL = default
@@ -320,9 +322,12 @@ int mgrit_solve_batch(int n, const mgrit_plan_t* plans,
 int mgrit_plan_set_coarse_solver(mgrit_plan_t plan, int mode);
 
 /* out[b] = Phi^k in[b] for b = 0..batch-1, rows of n_x values (device,
- * row-major, in and out may not overlap; k = 0 copies).  The fine stepper
- * of the plan in the plan's precision of relaxation; asynchronous on the
- * plan stream.  batch = 0 does nothing (in and out may then be NULL). */
+ * row-major, in and out may not overlap; k = 0 copies), Phi the fine time
+ * step u^{n+1} = Phi u^n of eq. (3) (Sec. 2.1; one collapsed stencil for ERK
+ * schemes, Corollary 1).  The fine stepper of the plan in the plan's
+ * precision of relaxation; asynchronous on the plan stream.  batch = 0 does
+ * nothing (in and out may then be NULL); MGRIT_EINVAL for a negative batch
+ * or k, or NULL rows. */
 int phi_apply_batch(mgrit_plan_t plan, const double* in_dev, double* out_dev,
                     int batch, int ksteps);
 
