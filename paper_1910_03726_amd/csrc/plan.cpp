@@ -1038,7 +1038,7 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
   for (int l = 1; l < levels; ++l) {
     n /= m;
     b += (size_t)(n + 1) * row;                                 // X_l
-    if (l < levels - 1) b += 2 * (size_t)(n / m + 1) * row;     // V_l, R_l
+    if (l < levels - 1) b += 3 * (size_t)(n / m + 1) * row;     // V_l, W_l, R_l
   }
   b += ((size_t)(nc + 1) * kMaxFineTiles + 1) * sizeof(double);  // partials, norm
   if (spectral_supported(nx))  // spectral coarsest solve: rows, eigenvalues, twiddles
@@ -1455,7 +1455,8 @@ static int plan_create(mgrit_plan_t* out, int nx, int nt, double alpha, double c
     for (int l = 1; l < levels; ++l) {
       Level& L = P->lev[l];
       if (!alloc(&L.X, L.n + 1)) return fail(MGRIT_ENOMEM);
-      if (l < levels - 1 && (!alloc(&L.V, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
+      if (l < levels - 1 &&
+          (!alloc(&L.V, L.nc + 1) || !alloc(&L.W, L.nc + 1) || !alloc(&L.R, L.nc + 1)))
         return fail(MGRIT_ENOMEM);
     }
     if (dev_alloc((void**)&P->partial, (size_t)(nc + 1) * kMaxFineTiles * sizeof(double)) !=
@@ -1561,6 +1562,7 @@ void mgrit_destroy(mgrit_plan_t plan) {
     L.seq.release();
     dev_free(L.X);
     dev_free(L.V);
+    dev_free(L.W);
     dev_free(L.R);
   }
   for (double* p : {P->Va, P->Vb, P->U, P->Rout, P->partial, P->d_norm, P->Sspec}) dev_free(p);

@@ -107,6 +107,7 @@ struct Level {
   OpDesc seq;        // coarsest level: single-workgroup sequential sweep
   double* X = nullptr;  // levels >= 2: all n+1 points (solution / correction)
   double* V = nullptr;  // levels >= 2 (not coarsest): relaxed C-points
+  double* W = nullptr;  // the same, of a cycle started from corrected C-points
   double* R = nullptr;  // C-point residuals = right-hand side of level l+1
 };
 

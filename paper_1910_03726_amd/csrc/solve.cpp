@@ -118,7 +118,12 @@ List live(const List& l) {
 // l-1.
 const double* rhs_of(const Member* M, int l) { return M->P->lev[l - 1].R; }
 
-void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec);
+// How a cycle on level l starts: from a zero guess, from the guess lev[l].X
+// (all points), or from the C-points lev[l].V corrected by lev[l+1].X (what
+// an interpolation would leave at the C-points).
+enum Start { START_ZERO, START_GUESS, START_CORRECTED };
+
+void cycle(Group& G, const List& l0, int l, Start start, int kind, int prec, bool interpolate);
 
 // Solve level l's error system (zero initial guess) into lev[l].X: on the
 // coarsest level by the sequential sweep, else by one V-cycle or by an
@@ -174,15 +179,20 @@ void coarse_solve(Group& G, const List& l0, int l, int kind, int prec) {
   }
   if (rest.empty()) return;
   if (kind == MGRIT_CYCLE_F) {
-    cycle(G, rest, l, true, MGRIT_CYCLE_F, prec);
-    cycle(G, rest, l, false, MGRIT_CYCLE_V, prec);
+    // The V-cycle's relaxation starts from the C-points and recomputes every
+    // F-point: of the F-cycle's interpolation only the corrected C-points
+    // v + e matter, and the V-cycle forms them as it reads them.
+    cycle(G, rest, l, START_ZERO, MGRIT_CYCLE_F, prec, false);
+    cycle(G, rest, l, START_CORRECTED, MGRIT_CYCLE_V, prec, true);
   } else {
-    cycle(G, rest, l, true, MGRIT_CYCLE_V, prec);
+    cycle(G, rest, l, START_ZERO, MGRIT_CYCLE_V, prec, true);
   }
 }
 
 // One V- or F-cycle on level l >= 1 (Sec. 4.4): relax, residual, coarse
-// solve, correct + F-relax.  Guess: lev[l].X (all points) unless `zero`.
+// solve, correct + F-relax (the last step left out when `interpolate` is
+// false: lev[l].V and lev[l+1].X then hold the relaxed C-points and their
+// correction).
 //
 // With FCF the C-point residual needs no right-hand side rows: the FC pass
 // gives v_{j+1} = Psi^m x_j + h_j (h_j the interval's propagated right-hand
@@ -190,17 +200,24 @@ void coarse_solve(Group& G, const List& l0, int l, int kind, int prec) {
 // pass also writes the update d = v - x, and the residual pass propagates d
 // alone: m right-hand side rows per interval less to read.  d is held in
 // lev[l+1].X, which the coarse solve overwrites only afterwards.
-void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec) {
+//
+// START_CORRECTED reads x = lev[l].V + lev[l+1].X, so the relaxed C-points
+// go to lev[l].W and d to lev[l].X (both unused until the interpolation).
+void cycle(Group& G, const List& l0, int l, Start start, int kind, int prec, bool interpolate) {
   List a = live(l0);
+  const bool corrected = start == START_CORRECTED;
   for (Member* M : a) {
     Plan* P = M->P;
     Level& L = P->lev[l];
-    const double* guess = zero ? nullptr : L.X;
+    const double* guess = start == START_ZERO ? nullptr : corrected ? L.V : L.X;
+    const long long stride = corrected ? 1 : P->m;
+    const double* corr = corrected ? P->lev[l + 1].X : nullptr;
+    double* v = corrected ? L.W : L.V;
     if (P->relax_kind == MGRIT_RELAX_FCF)
-      Group::check(M, P->relax(l, prec, MODE_FC, guess, P->m, nullptr, rhs_of(M, l), RHS_EVERY,
-                               L.V, nullptr, P->m, P->lev[l + 1].X));
+      Group::check(M, P->relax(l, prec, MODE_FC, guess, stride, corr, rhs_of(M, l), RHS_EVERY,
+                               v, nullptr, P->m, corrected ? L.X : P->lev[l + 1].X));
     else  // F-relaxation only: v = u
-      Group::check(M, P->copy_cpoints(l, prec, guess, P->m, nullptr, L.V));
+      Group::check(M, P->copy_cpoints(l, prec, guess, stride, corr, v));
   }
   G.flush(a);
   a = live(a);
@@ -208,20 +225,21 @@ void cycle(Group& G, const List& l0, int l, bool zero, int kind, int prec) {
     Plan* P = M->P;
     Level& L = P->lev[l];
     if (P->relax_kind == MGRIT_RELAX_FCF)
-      Group::check(M, P->relax(l, prec, MODE_FC, P->lev[l + 1].X, 1, nullptr, nullptr, RHS_NONE,
-                               L.R, nullptr, P->m));
+      Group::check(M, P->relax(l, prec, MODE_FC, corrected ? L.X : P->lev[l + 1].X, 1, nullptr,
+                               nullptr, RHS_NONE, L.R, nullptr, P->m));
     else
-      Group::check(M, P->relax(l, prec, MODE_RES, L.V, 1, nullptr, rhs_of(M, l), RHS_EVERY, L.R,
-                               nullptr, P->m));
+      Group::check(M, P->relax(l, prec, MODE_RES, corrected ? L.W : L.V, 1, nullptr,
+                               rhs_of(M, l), RHS_EVERY, L.R, nullptr, P->m));
   }
   G.flush(a);
   coarse_solve(G, a, l + 1, kind, prec);
+  if (!interpolate) return;
   a = live(a);
   for (Member* M : a) {
     Plan* P = M->P;
     Level& L = P->lev[l];
-    Group::check(M, P->relax(l, prec, MODE_F, L.V, 1, P->lev[l + 1].X, rhs_of(M, l), RHS_EVERY,
-                             L.X, nullptr, P->m));
+    Group::check(M, P->relax(l, prec, MODE_F, corrected ? L.W : L.V, 1, P->lev[l + 1].X,
+                             rhs_of(M, l), RHS_EVERY, L.X, nullptr, P->m));
   }
   G.flush(a);
 }
