@@ -1047,21 +1047,19 @@ size_t plan_state_bytes(int nx, int nt, int m, int levels, int precision) {
 }
 
 // Modelled time of one spectral coarsest-level solve of n steps (row
-// transforms, mode recurrences, inverse transforms), fitted to MI355X
-// measurements (4096-point rows x 32 steps, 2048 x 512, 8192 x 16, within
-// about 10 %): launch costs, about 3.4 us per four-stage pass of a
-// transform per group of 16 points a thread takes, a dependent load round
-// trip of about 1.2 us per 16 steps of the recurrences, 64 bytes of HBM
-// traffic per point and step at 6 TB/s.
+// transforms, mode recurrences, inverse transforms) on MI355X: a fixed part
+// per row length (the three launches and the latency of one row's
+// transforms, measured at each power of two from 512 up; 14 us below) plus
+// 11 ps per point and step (the solve's 80 bytes of traffic per point and
+// step at about 7 TB/s).  Fitted to 16 measured shapes, n_x = 512..8192 and
+// n = 16..1024: within 20 %.
 static double spectral_time_us(int nx, int n) {
+  // fixed part at n_x = 2^8 .. 2^13
+  static const double base[] = {14.0, 14.7, 16.2, 17.8, 20.0, 31.5};
   int lg = 0;
   while ((1 << lg) < nx) ++lg;
-  const int passes = (lg + 3) / 4;
-  // a row transform: per pass, each of the 256 threads takes ceil(nx/4096)
-  // groups of 16 points (3.4 us per group and pass); rows run in parallel
-  const int groups = (nx + 4095) / 4096;
-  return 3 * 3.0 + 2 * (3.4 * passes * groups) + 2.0 + ((n + 15) / 16) * 1.2 +
-         (double)(n + 1) * nx * 64.0 / 6.0e6;
+  const double b = base[std::min(std::max(lg, 8), 13) - 8];
+  return b + 1.1e-5 * (double)(n + 1) * nx;
 }
 
 int Plan::set_coarse_mode(int mode) {

@@ -78,3 +78,19 @@ def test_spectral_needs_a_power_of_two():
         assert e.value.code == M.EINVAL
         P.set_coarse_solver("sweep")
         assert "(spectral solve)" not in P.describe()
+
+
+@pytest.mark.parametrize("nx", [1 << lg for lg in range(2, 14)])
+def test_every_transform_size_matches_sequential_stepping(nx):
+    # one transform kernel per size n_x/2 = 2, 4, ..., 4096 complex points;
+    # a row of random values (all modes present) stepped 64 ERK3 steps
+    scheme, nt, m = "ERK3", 64, 4
+    P, c = _plan(scheme, nx, nt, m, 2, "V", "fp64", "spectral")
+    u0n = np.random.default_rng(nx).standard_normal(nx)
+    with P:
+        assert "(spectral solve)" in P.describe()
+        r = P.solve(torch.tensor(u0n, device="cuda"), None, tol=1e-13, maxit=40, out="final")
+        assert r.status == M.OK
+    ref = rk.Discretization(scheme, nx, c).propagate(u0n, nt)
+    got = r.out.cpu().numpy()[0]
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
