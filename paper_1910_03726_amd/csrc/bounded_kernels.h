@@ -389,11 +389,14 @@ __device__ __forceinline__ double shl1(double old, double v) {
 // kRegLen weights, held in registers) over bu.  bu
 // holds, per step parity, the left region's points, lane a's chunk, lane
 // b-1's chunk and the right region's points; lanes a and b-1 export their
-// chunks there before the barrier.  After the barrier region lanes take
-// their points of the step from bu (their own stencil results are
-// discarded) before the DPP shifts, so every non-region lane reads true
-// values; a and b are no multiples of 64, so a region lane never feeds a
-// non-region lane through a wavefront-edge slot.  The inflow forcing (rows
+// chunks there before the barrier.  Region lanes keep running the stencil
+// on stale points (their results are discarded); after the barrier lane
+// a-1 takes its last HL points and lane b its first HR points of the step
+// from bu before the DPP shifts, so every non-region lane reads true
+// values (a and b are no multiples of 64, so a region lane never feeds a
+// non-region lane through a wavefront-edge slot), and every region lane
+// takes all its points from bu after the last step.  With MODE_F the last
+// wavefront stores the region points of every step.  The inflow forcing (rows
 // < nf <= a*K) is added there too, staged in LDS before the first step (in
 // blocks of kRegFCap / nf steps when m * nf exceeds kRegFCap).  The two
 // kinds of wavefront run loops of their own with the same barriers.
@@ -509,16 +512,22 @@ __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j
         for (int k = K - XB; k < K; ++k) bcur[LW + k] = x[k];
       }
       lds_barrier();
-      // region lanes: the true points of state s
-      if (pslot != -1) {
+      // region lanes hold stale points between steps; only lane a-1's last
+      // HL and lane b's first HR points reach other lanes (the DPP shifts),
+      // so only those are taken from bu (the rest after the last step)
+      if (tid == ra - 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) x[k] = pslot >= 0 ? bcur[pslot + k] : 0.0;
+        for (int h = 0; h < HL; ++h) x[K - HL + h] = bcur[ra * K - HL + h];
       }
-      if (store_steps && s >= 1) {
+      if (tid == rb) {
+#pragma unroll
+        for (int h = 0; h < HR; ++h) x[h] = bcur[LW + K + h];
+      }
+      // state s (region points: stored by the last wavefront)
+      if (store_steps && s >= 1 && pslot == -1) {
         double* orow = a.out + (row0 + s) * nx;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-          if (tid * K + k < nx) orow[tid * K + k] = x[k];
+        for (int k = 0; k < K; ++k) orow[tid * K + k] = x[k];
       }
       double el[HL > 0 ? HL : 1], er[HR > 0 ? HR : 1];
 #pragma unroll
@@ -611,6 +620,13 @@ __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j
         for (int q = lw; q < n; q += 64) fst[q] = Fs[q];
       }
       lds_barrier();
+      if (store_steps && s >= 1) {
+        // state s of the region points
+        double* orow = a.out + (row0 + s) * nx;
+        const double* bc = bu + par * BU;
+        for (int q = lw; q < ra * K; q += 64) orow[q] = bc[q];
+        for (int q = lw; q < nx - rb * K; q += 64) orow[rb * K + q] = bc[LW + K + q];
+      }
       if (act) {
         const double* ur = bu + par * BU + rcs;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
