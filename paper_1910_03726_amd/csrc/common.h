@@ -73,6 +73,14 @@ struct RelaxArgs {
                            // rows staged in LDS before the first step
 };
 
+// Stencil kernels without per-step I/O whose halo comes by lane shifts
+// (window W - 1 <= K) stage their start and end rows through LDS one half
+// of the extent at a time: half the LDS, so more workgroups per CU.
+constexpr bool kHalfStage = true;
+constexpr bool stencil_half_stage(int K, int W, bool io) {
+  return kHalfStage && !io && W - 1 <= K && K % 2 == 0;
+}
+
 // Inflow forcing values (steps x nf) the lane-resident bounded kernel stages
 // in LDS at a time.
 constexpr int kRegFCap = 256;

@@ -28,9 +28,11 @@ namespace mgr {
 // kernel selection
 // ---------------------------------------------------------------------------
 // LDS bytes of k_stencil for an extent of E points, chunk K, NL lanes,
-// compiled width Wb and state element size el.
-static size_t stencil_lds(int E, int K, int NL, int Wb, size_t el) {
-  const size_t stage = sizeof(double) * (size_t)(E + E / K);
+// compiled width Wb, state element size el and per-step I/O io (the
+// staging area holds half the extent when stencil_half_stage).
+static size_t stencil_lds(int E, int K, int NL, int Wb, size_t el, bool io) {
+  const int Es = stencil_half_stage(K, Wb, io) ? E / 2 : E;  // staged positions
+  const size_t stage = sizeof(double) * (size_t)(Es + Es / K);
   if (Wb - 1 <= K) {
     const int H = std::min(Wb - 1, K);
     return stage + 2 * (size_t)(NL / 64) * std::max(H, 1) * el;
@@ -146,8 +148,8 @@ static bool finish_shape(StencilShape& sh, int E, int Wb, bool io) {
   const KernelTable& kt = kernel_table();
   const int ki = k_index(sh.K), wi = width_index(Wb);
   if (ki < 0 || wi < 0) return false;
-  sh.shmem[0] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(double));
-  sh.shmem[1] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(float));
+  sh.shmem[0] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(double), io);
+  sh.shmem[1] = stencil_lds(E, sh.K, sh.NL, Wb, sizeof(float), io);
   if (sh.shmem[0] > 160 * 1024) return false;
   for (int q = 0; q < 2; ++q) {
     sh.fn[q] = kt.stencil[q][ki][wi][io ? 1 : 0];

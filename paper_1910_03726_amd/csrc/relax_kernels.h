@@ -265,6 +265,17 @@ struct Extent {
 #pragma unroll
     for (int q = 0; q < K; ++q) stg[slot(lane + q * NL)] = r[q];
   }
+  // the same for half h of the extent (positions h E/2 + lane + q NL,
+  // q < K/2) into a staging area of half the size
+  __device__ __forceinline__ void fetch_half(const double* row, int h, double (&r)[K / 2]) const {
+    const int b = first(0) + h * (E / 2);
+#pragma unroll
+    for (int q = 0; q < K / 2; ++q) r[q] = ld_row(row, at(b, lane + q * NL));
+  }
+  __device__ __forceinline__ void put_half(double* stg, const double (&r)[K / 2]) const {
+#pragma unroll
+    for (int q = 0; q < K / 2; ++q) stg[slot(lane + q * NL)] = r[q];
+  }
   // this lane's chunk of a row, straight from global memory
   __device__ __forceinline__ void chunk(const double* row, int sh, double (&r)[K]) const {
     const int b = first(sh);
@@ -276,18 +287,15 @@ struct Extent {
 // Stores after the last step of a stencil workgroup (MODE_FC / MODE_RES):
 // the tile's positions [eout, E) of the state x (frame shift sh), staged
 // for coalesced access; residuals and their partial sum (one per
-// workgroup, at partial[j * tiles + c], i.e. at its block index).
-template <typename T, int K>
+// workgroup, at partial[j * tiles + c], i.e. at its block index).  HALF:
+// the staging area holds half the extent, so the lanes of each half stage
+// their chunks in turn.
+template <typename T, int K, bool HALF>
 __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, int blk, const Extent<K>& X,
                                               int eout, int sh, const T (&x)[K], double* stg,
                                               double* red) {
   if (a.mode != MODE_FC && a.mode != MODE_RES) return;
   const int nx = a.nx, NL = X.NL, lane = X.lane, E = X.E;
-  __syncthreads();  // the image / staging area is no longer read
-  const int b = lane * (K + 1);
-#pragma unroll
-  for (int k = 0; k < K; ++k) stg[b + k] = (double)x[k];
-  __syncthreads();
   const int bs = X.first(sh);
   const long long rj = (long long)(j + 1) * nx;
   const double* grow = a.rhs_mode == RHS_CPOINT ? a.rhs + rj : nullptr;
@@ -299,20 +307,45 @@ __device__ __forceinline__ void finish_extent(const RelaxArgs& a, int j, int blk
   const double* crow = (dl && a.corr) ? a.corr + (long long)(j + 1) * a.corr_stride * nx : nullptr;
   double* drow = dl ? a.delta + rj : nullptr;
   double ss = 0.0;
+  // position e of the extent, its staged value v
+  auto emit = [&](int e, double v) __attribute__((always_inline)) {
+    const unsigned g = X.at(bs, e);
+    if (grow) v += ld_row(grow, g);
+    if (rrow) v -= ld_row(rrow, g);
+    ss += v * v;
+    st_row(orow, g, v);
+    if (dl) {
+      double u = urow ? ld_row(urow, g) : 0.0;
+      if (crow) u += ld_row(crow, g);
+      st_row(drow, g, v - u);
+    }
+  };
+  if constexpr (!HALF) {
+    __syncthreads();  // the image / staging area is no longer read
+    const int b = lane * (K + 1);
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const int e = eout + lane + q * NL;
-    if (e < E) {
-      const unsigned g = X.at(bs, e);
-      double v = stg[Extent<K>::slot(e)];
-      if (grow) v += ld_row(grow, g);
-      if (rrow) v -= ld_row(rrow, g);
-      ss += v * v;
-      st_row(orow, g, v);
-      if (dl) {
-        double u = urow ? ld_row(urow, g) : 0.0;
-        if (crow) u += ld_row(crow, g);
-        st_row(drow, g, v - u);
+    for (int k = 0; k < K; ++k) stg[b + k] = (double)x[k];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      const int e = eout + lane + q * NL;
+      if (e < E) emit(e, stg[Extent<K>::slot(e)]);
+    }
+  } else {
+    // half h: lanes [h NL/2, (h+1) NL/2), positions [h E/2, (h+1) E/2)
+    const int hl = NL / 2, EH = E / 2;
+    for (int h = 0; h < 2; ++h) {
+      __syncthreads();  // the staging area is no longer read
+      if ((lane >= hl) == (h == 1)) {
+        const int b = (lane - h * hl) * (K + 1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) stg[b + k] = (double)x[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < K / 2; ++q) {
+        const int e = lane + q * NL;  // within the half
+        if (h * EH + e >= eout) emit(h * EH + e, stg[Extent<K>::slot(e)]);
       }
     }
   }
@@ -379,7 +412,9 @@ __device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) 
   int f0 = (t1 - E) % nx;
   f0 += (f0 < 0) ? nx : 0;
   const Extent<K> X{nx, NL, lane, E, f0};
-  const int nst = E + E / K;  // doubles of one staged row
+  // start and end rows staged half the extent at a time
+  constexpr bool HALF = stencil_half_stage(K, W, IO);
+  const int nst = HALF ? E / 2 + E / 2 / K : E + E / K;  // doubles of the staging area
   const bool preload = IO && a.preload && a.rhs_mode == RHS_EVERY;
   double* ring = reinterpret_cast<double*>(smem_raw);  // preloaded rows 1..m
   unsigned char* lds = smem_raw + (preload ? sizeof(double) * (size_t)m * nst : 0);
@@ -406,7 +441,49 @@ __device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) 
   };
 
   // start state (FP64, staged)
-  {
+  const bool store0 = (a.mode == MODE_F && !a.skip_row0) ||
+                      (a.mode == MODE_FC && a.write_row0 && j == 0);
+  T x[K];
+  if constexpr (HALF) {
+    // each half fetched (coalesced), staged and taken by its lanes in turn:
+    // half the LDS and half a row in registers
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      double v[K / 2];
+      if (a.zero_in) {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) v[q] = 0.0;
+      } else {
+        X.fetch_half(a.in + (long long)j * a.in_stride * nx, h, v);
+        const double* adds[3] = {a.corr ? a.corr + (long long)j * a.corr_stride * nx : nullptr,
+                                 a.sub ? a.sub + (long long)j * nx : nullptr,
+                                 a.sub2 ? a.sub2 + (long long)j * nx : nullptr};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          if (!adds[r]) continue;
+          double w[K / 2];
+          X.fetch_half(adds[r], h, w);
+#pragma unroll
+          for (int q = 0; q < K / 2; ++q) v[q] += r == 0 ? w[q] : -w[q];
+        }
+      }
+      if (store0) {
+        double* row = a.out + (a.mode == MODE_F ? (long long)j * m * nx : 0LL);
+        const int b0 = X.first(0) + h * (E / 2);
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q)
+          if (h * (E / 2) + lane + q * NL >= eout) st_row(row, X.at(b0, lane + q * NL), v[q]);
+      }
+      if (h == 1) __syncthreads();  // the first half has been taken
+      X.put_half(stg, v);
+      __syncthreads();
+      if ((lane >= NL / 2) == (h == 1)) {
+        const int bh = b - h * (NL / 2) * (K + 1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) x[k] = (T)stg[bh + k];
+      }
+    }
+  } else {
     double v[K];
     if (a.zero_in) {
 #pragma unroll
@@ -435,26 +512,29 @@ __device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) 
       }
     }
     X.put(stg, v);
-  }
-  __syncthreads();
-  const bool store0 = (a.mode == MODE_F && !a.skip_row0) ||
-                      (a.mode == MODE_FC && a.write_row0 && j == 0);
-  if (store0) {
-    double* row = a.out + (a.mode == MODE_F ? (long long)j * m * nx : 0LL);
-    const int b0 = X.first(0);
+    __syncthreads();
+    if (store0) {
+      double* row = a.out + (a.mode == MODE_F ? (long long)j * m * nx : 0LL);
+      const int b0 = X.first(0);
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-      const int e = eout + lane + q * NL;
-      if (e < E) st_row(row, X.at(b0, e), stg[Extent<K>::slot(e)]);
+      for (int q = 0; q < K; ++q) {
+        const int e = eout + lane + q * NL;
+        if (e < E) st_row(row, X.at(b0, e), stg[Extent<K>::slot(e)]);
+      }
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = (T)stg[b + k];
   }
   if (a.mode == MODE_F && j == a.nint) return;  // extra block: the last C-point
-  T x[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) x[k] = (T)stg[b + k];
+  // the taps through the scalar cache (read only): FP64 taps stay in
+  // scalar registers, which the FMAs take as operands
   T tp[W];
+  {
+    typedef __attribute__((address_space(4))) const double cdouble;
+    const cdouble* tq = (const cdouble*)a.taps;
 #pragma unroll
-  for (int t = 0; t < W; ++t) tp[t] = (T)a.taps[t];
+    for (int t = 0; t < W; ++t) tp[t] = (T)tq[t];
+  }
   wait_vmem();
 
   const bool every = IO && a.rhs_mode == RHS_EVERY;
@@ -632,7 +712,7 @@ __device__ __forceinline__ void stencil_body(const RelaxArgs& a, const int blk) 
   if (!every) run(std::false_type{}, std::false_type{});
   else if (preload) run(std::true_type{}, std::true_type{});
   else run(std::true_type{}, std::false_type{});
-  finish_extent<T, K>(a, j, blk, X, eout, sh, x, stg, red);
+  finish_extent<T, K, HALF>(a, j, blk, X, eout, sh, x, stg, red);
 }
 
 template <typename T, int K, int W, bool IO>
