@@ -82,6 +82,26 @@ def test_phi_apply_batch_fp32(scheme, nx):
         assert _rel(_n(out), d.propagate(U, 5)) < 2e-5
 
 
+def test_tiled_fine_passes_match_the_oracle():
+    # plans of one interval tile the fine level over several workgroups
+    # ("plain:" shape); a tile's start and end rows are staged half the
+    # extent at a time and only its own positions are written
+    tiled = 0
+    for scheme, nx in (("ERK1", 8192), ("ERK3", 4096), ("ERK3", 8192), ("ERK5", 8192)):
+        c = rk.paper_cfl(scheme)
+        d = rk.Discretization(scheme, nx, c)
+        with M.Plan(nx, 4, c, scheme, 4, 2, IDENT) as P:
+            fine = P.describe().split(";")[0]
+            tiled += "plain:" in fine
+            U = np.random.default_rng(nx).standard_normal((3, nx))
+            out = torch.empty((3, nx), dtype=torch.float64, device=DEV)
+            for k in (1, 3, 4):
+                P.phi_apply_batch(_t(U), out, k)
+                torch.cuda.synchronize()
+                assert _rel(_n(out), d.propagate(U, k)) < 2e-14 * k, (fine, k)
+    assert tiled >= 1
+
+
 def test_phi_apply_long_sequential():
     # GPU sequential time-stepping (batch 1, k = n_t) against the oracle:
     # random-walk rounding keeps the relative error far below 1e-12.
