@@ -406,14 +406,16 @@ __device__ __forceinline__ double shl1(double old, double v) {
 //
 // LDS: the staging area NL*(K+1) doubles (start and end rows, coalesced),
 // the edge slots 2 * NL/64 * (HL+HR), bu 2 * rg_bu, the forcing kRegFCap:
-// under 40 KB for n_x = 4096, four workgroups per CU.
+// under 40 KB for n_x = 4096, four workgroups per CU.  Registers are held
+// to six wavefronts per SIMD (76 VGPRs): a workgroup of five wavefronts
+// places two on one SIMD, and at five per SIMD only three workgroups fit.
 template <int K, int HL, int HR>
 __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j) {
   constexpr int W = HL + HR + 1;
   constexpr int HE = HL + HR;  // doubles of one wavefront's edge slots
   constexpr int XB = kRegExportB<K, HL>();
-  constexpr int BL = 13;       // loads per thread in flight (row traffic):
-                               // one round trip per row for n_x = 4096
+  constexpr int BL = 10;       // loads per thread in flight (row traffic):
+                               // more would not fit six wavefronts per SIMD
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[16];
   const BoundedDev* bd = reinterpret_cast<const BoundedDev*>(a.opdata);
@@ -484,8 +486,14 @@ __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j
     const int pslot =
         tid < ra ? tid * K : (tid >= rb ? (tid < nla ? LW + (tid - rb + 1) * K : -2) : -1);
     double c[W];
+    {
+      // through the scalar cache (read only): the taps stay in scalar
+      // registers, which the FMAs take as operands
+      typedef __attribute__((address_space(4))) const double cdouble;
+      const cdouble* tq = (const cdouble*)a.taps;
 #pragma unroll
-    for (int i = 0; i < W; ++i) c[i] = a.taps[i];
+      for (int i = 0; i < W; ++i) c[i] = tq[i];
+    }
     const int eo = wave * HE;
 #pragma unroll
     for (int k = 0; k < K; ++k) x[k] = stg[tid * (K + 1) + k];
@@ -630,11 +638,11 @@ __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j
       if (act) {
         const double* ur = bu + par * BU + rcs;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        // in two halves: at most half the window's reads in registers
+        // in thirds: at most a third of the window's reads in registers
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 3; ++h) {
 #pragma unroll
-          for (int t = h * kRegLen / 2; t < (h + 1) * kRegLen / 2; t += 4) {
+          for (int t = h * kRegLen / 3; t < (h + 1) * kRegLen / 3; t += 4) {
             s0 = fma(cr[t], ur[t], s0);
             s1 = fma(cr[t + 1], ur[t + 1], s1);
             s2 = fma(cr[t + 2], ur[t + 2], s2);
@@ -689,12 +697,12 @@ __device__ __forceinline__ void bounded_reg_body(const RelaxArgs& a, const int j
 }
 
 template <int K, int HL, int HR>
-__global__ void __launch_bounds__(1024, 5) k_bounded_reg(RelaxArgs a) {
+__global__ void __launch_bounds__(1024, 6) k_bounded_reg(RelaxArgs a) {
   bounded_reg_body<K, HL, HR>(a, (int)blockIdx.x);
 }
 
 template <int K, int HL, int HR>
-__global__ void __launch_bounds__(1024, 5) k_bounded_reg_b(BatchArgs b) {
+__global__ void __launch_bounds__(1024, 6) k_bounded_reg_b(BatchArgs b) {
   int blk;
   const RelaxArgs a = batch_member(b, blk);
   bounded_reg_body<K, HL, HR>(a, blk);
