@@ -90,6 +90,26 @@ def test_lane_kernel_steps_like_the_oracle(case):
             assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), (k, s, nx)
 
 
+@pytest.mark.parametrize("case", LANE_CASES[2:], ids=[f"{c[0]}-{c[1]}" for c in LANE_CASES[2:]])
+def test_lane_kernel_full_output(case):
+    # the whole space-time solution (out="all"): the converged C-points
+    # F-relaxed by the lane-resident kernel, every state of every interval
+    # stored (the interior by its lanes, the boundary regions by the extra
+    # wavefront), against the oracle's sequential stepping
+    s, nx, K = case
+    nt, m = 48, 4
+    d, c, H, psi, G = _setup(s, nx, nt, m, 2)
+    u0 = inputs.fourier_u0(nx, 4, 2)
+    with M.Plan(nx, nt, c, s, m, 2, psi, inflow=G) as P:
+        assert f"bounded_lanes<K={K}," in P.describe()
+        r = P.solve(torch.tensor(u0, device="cuda"), None, tol=1e-13, maxit=60, out="all")
+    assert r.status == M.OK
+    seq = d.time_stepping(u0, G, every=1)
+    got = r.out.cpu().numpy()
+    assert got.shape == seq.shape
+    assert np.max(np.abs(got - seq)) <= 1e-11 * np.max(np.abs(seq))
+
+
 CASES = [
     # scheme, nx, nt, m, levels, cycle, relax, widths
     ("ERK1", 256, 1024, 4, 2, "V", "FCF", [3]),
