@@ -213,6 +213,17 @@ def test_parareal_f_relaxation_counts():
     _check_hist(g, R)
 
 
+@pytest.mark.parametrize("scheme,nx,nt,m,levels", [("ERK3", 128, 1024, 4, 3),
+                                                   ("ERK3", 128, 2048, 4, 4),
+                                                   ("ERK1", 128, 1024, 4, 3)])
+def test_f_cycles_with_f_relaxation(scheme, nx, nt, m, levels):
+    # F-relaxation only inside F-cycles: the V-cycle that follows an
+    # F-cycle on a level starts from the corrected C-points v + e
+    _, R, g, _ = _compare(scheme, nx, nt, m, levels, cycle="F", relax="F")
+    assert R.status == "converged"
+    _check_hist(g, R)
+
+
 def test_exactness_with_rediscretized_psi():
     # Rediscretized Psi diverges (coarse CFL 3.4); FCF is exact after
     # n_t/(2m) = 32 iterations: the residual is exactly zero on the GPU too.
